@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Fused-depth frames/s on the paper-scale frame: 1242x375, D = 128, 9x7
+census, 8 SGM paths, SDSGM (semidensification + DDC), parabola subpixel and
+the stereo-LiDAR consistency check, Tab. II parameters.
+
+One step = the whole hot path (LiDAR ingest, census, semidensification,
+fused cost + 8-path aggregation for both views, WTA + subpixel, check) over a
+batch of seeded synthetic frames already resident in HBM.  Prints one JSON
+line: throughput (frames/s), single-frame latency p50/p99, a roofline entry
+for the dominant kernel (the SGM path pass) timed live with HIP events on the
+stream it runs on, and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fused-depth frames/s @1242x375 D=128, plain vs learned-check; p99 latency"
+W, H, D = 1242, 375, 128
+
+# MI355X vector ALU peaks: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T
+# 32-bit lane-ops/s; packed 2 x 16-bit instructions double that (78.6 T).
+PEAK_OPS32 = 256 * 64 * 2.4e9
+PEAK_OPS16 = 2 * PEAK_OPS32
+
+
+def sgm_ops_per_launch(frames: int, views: int):
+    """Algorithmic integer ops of one SGM path pass (one direction, both
+    views, all frames).  Per cell (pixel x disparity): the Eq. 2 step is 9
+    ops (two +P1, three mins, -m, +C, running min, +S) on 16-bit data; the
+    joint cost is xor + popcount (32-bit) plus the (1-alpha) scaling and, in
+    the left view, the DDC add (16-bit)."""
+    cells = frames * W * H * D
+    ops32 = 2 * cells * views
+    ops16 = cells * (9 + 2) + (views - 1) * cells * (9 + 1)
+    return ops16, ops32
+
+
+def cpu_baseline(n_frames: int):
+    import oracle
+    from paper_2504_05148_amd import synth
+    frames = [synth.kitti_frame(1000 + i) for i in range(n_frames)]
+    P = oracle.OracleParams()
+    lids = [oracle.quantize_lidar(f["lidar"], D) for f in frames]
+    t0 = time.perf_counter()
+    for f, lid in zip(frames, lids):
+        oracle.run(P, f["left"], f["right"], lid)
+    dt = time.perf_counter() - t0
+    return dict(value=n_frames / dt, unit="frames/s", cores=1, kind="oracle",
+                sample=f"{n_frames} synthetic 1242x375 D=128 frames, full method, "
+                       f"single-threaded C oracle ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=8, help="frames per step")
+    ap.add_argument("--latency-runs", type=int, default=200)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus must be 1 "
+              "(frames are independent, so more GPUs would each run their own "
+              "frame stream with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_05148_amd import sldf, synth
+
+    torch.cuda.set_device(0)
+    B = args.batch
+    t_gen = time.perf_counter()
+    frames = [synth.kitti_frame(i) for i in range(B)]
+    print(f"[bench] generated {B} frames in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    left = sldf.device_images(np.stack([f["left"] for f in frames]))
+    right = sldf.device_images(np.stack([f["right"] for f in frames]))
+    lid_f = torch.from_numpy(np.stack([f["lidar"] for f in frames])).cuda().contiguous()
+    lid_q = torch.empty((B, H, W), dtype=torch.int16, device="cuda")
+
+    p = sldf.default_params(batch=B)
+    ctx = sldf.Context(p)
+    disp, valid = ctx.new_outputs(B)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        # ingest (float LiDAR -> D-bar) + the whole method for B frames
+        sldf.quantize_lidar(lid_f.view(B * H, W), D, out=lid_q.view(B * H, W))
+        ctx.run_batch(left, right, lid_q, disp, valid)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    K = args.steps
+    ctx.timing_enable(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = ctx.timing_read()
+    ctx.timing_enable(0)
+    elapsed = t1 - t0
+    fps = K * B / elapsed
+    print(f"[bench] {K} steps x {B} frames in {elapsed * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel: the SGM path pass
+    sgm_ms, sgm_launches = stages["sgm"]
+    avg_launch_s = sgm_ms / 1e3 / max(sgm_launches, 1)
+    ops16, ops32 = sgm_ops_per_launch(B, 2)
+    floor_s = ops16 / PEAK_OPS16 + ops32 / PEAK_OPS32
+    peak = (ops16 + ops32) / floor_s
+    achieved = (ops16 + ops32) / avg_launch_s
+    roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
+                    unit="Tops/s", frac=round(achieved / peak, 4), traffic=None,
+                    kernel="sgm_dir_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
+                    ops_per_launch=int(ops16 + ops32))
+    stage_ms = {k: round(v[0] / (K * B), 4) for k, v in stages.items()}
+
+    # latency mode: one frame at a time on an idle GPU
+    p1 = sldf.default_params(batch=1)
+    ctx1 = sldf.Context(p1)
+    d1, v1 = ctx1.new_outputs()
+    lq1 = torch.empty((H, W), dtype=torch.int16, device="cuda")
+    lats = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(args.latency_runs + 5):
+        j = i % B
+        ev0.record(stream)
+        sldf.quantize_lidar(lid_f[j], D, out=lq1)
+        ctx1.run(left[j], right[j], lq1, d1, v1)
+        ev1.record(stream)
+        ev1.synchronize()
+        if i >= 5:
+            lats.append(ev0.elapsed_time(ev1))
+    lats = np.array(lats)
+    print(f"[bench] latency p50 {np.percentile(lats, 50):.3f} ms", file=sys.stderr, flush=True)
+
+    out = dict(metric=METRIC, value=round(fps, 2), unit="frames/s", n_gpus=1, steps=K,
+               warmup=args.warmup, ms_per_step=round(elapsed / K * 1e3, 4),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u16",
+               data="synthetic",
+               config=dict(workload="1242x375 D=128 census9x7 8-path SDSGM + DDC + "
+                                    "stereo-LiDAR check (Tab. II), plain check",
+                           frames_per_step=B, width=W, height=H, max_disp=D,
+                           check="plain", parallelism="single GPU, batched frames"),
+               latency_ms=dict(p50=round(float(np.percentile(lats, 50)), 4),
+                               p99=round(float(np.percentile(lats, 99)), 4),
+                               runs=int(lats.size)),
+               stage_ms_per_frame=stage_ms, roofline=roofline, learned_check=None)
+    if not args.no_cpu_baseline and args.cpu_frames > 0:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

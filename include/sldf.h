@@ -1,0 +1,200 @@
+/*
+ * sldf.h -- C ABI of the MI355X (gfx950) stereo-LiDAR depth-fusion library
+ * libsldf.so.
+ *
+ * The library computes, per frame, the method of "Stereo-LiDAR Fusion by
+ * Semi-Global Matching with Discrete Disparity-Matching Cost and
+ * Semidensification" (Yao, Ishikawa, Oishi, IEEE RA-L 2025):
+ *   inputs   a rectified uint8 stereo pair (left image = base) and a sparse
+ *            LiDAR disparity map D-bar aligned with the left image
+ *            (Sec. IV, definition of D-bar: values in N or "invalid");
+ *   steps    semidensification (Sec. IV-B, Eq. 5; SDSGM variant only),
+ *            census Hamming cost + discrete disparity-matching cost
+ *            (Sec. IV-A, Eq. 4), multi-path SGM aggregation (Sec. III,
+ *            Eq. 2), winner-takes-all (Eq. 3) with parabola subpixel fit,
+ *            the right-view SGM pass and the stereo-LiDAR consistency check
+ *            (Sec. IV-C, Eq. 6);
+ *   output   a dense float32 disparity map with invalid pixels (-1.0f) and a
+ *            uint8 validity mask (the consistent map D^{c*} of Eq. 6).
+ *
+ * Conventions
+ *   - Every function returns an sldf_status and never aborts or throws.
+ *   - "device" pointers are HIP device memory on the device that was current
+ *     when the context was created; "host" pointers are ordinary memory.
+ *   - Pitches are in ELEMENTS of the array's own type (bytes for uint8).
+ *   - All GPU work is enqueued on the caller's HIP stream (hipStream_t passed
+ *     as void*; NULL = the null stream).  No call synchronises the host and
+ *     no call allocates device memory after sldf_create: the workspace is
+ *     caller-owned and sldf_workspace_size() is the exact HBM cost.
+ *   - A context may be used by one stream at a time; separate contexts may run
+ *     concurrently on separate streams.
+ *
+ * Readings of the paper fixed by this ABI (the CPU oracle uses the same):
+ *   alpha = alpha_num / alpha_den is applied exactly by scaling every cost
+ *   term by alpha_den: C' = (den - num) H + num DDC, P1' = den P1,
+ *   P2' = den P2 (argmin and subpixel offset are scale invariant); census
+ *   is the centre-symmetric census with bit k = [I(p+o_k) > I(p-o_k)] over
+ *   the raster-order first half of the window, 0 where the window leaves the
+ *   image; the Hamming cost is n (all bits) where the matching pixel leaves
+ *   the image; ties in WTA and semidensification go to the smallest d; the
+ *   right-view disparity d' is a full right-base SGM without prior; the
+ *   check uses the integer d* and the raw LiDAR map.
+ */
+#ifndef SLDF_H
+#define SLDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLDF_ABI_VERSION 1
+
+typedef enum {
+    SLDF_OK = 0,
+    SLDF_EINVAL = -1,    /* invalid argument or parameter value */
+    SLDF_ESHAPE = -2,    /* width / height / disparity range out of range */
+    SLDF_EALIGN = -3,    /* pointer or pitch alignment violated */
+    SLDF_EOVERFLOW = -4, /* parameters could overflow the 16-bit cost sums */
+    SLDF_ENOMEM = -5,    /* workspace too small / host allocation failed */
+    SLDF_EDEVICE = -6,   /* a HIP call or kernel launch failed */
+    SLDF_ESTATE = -7     /* context used in a state that does not allow it */
+} sldf_status;
+
+/* Method parameters.  Tab. II values are the defaults (sldf_params_default). */
+typedef struct {
+    int32_t struct_size;   /* sizeof(sldf_params): ABI check */
+    int32_t width;         /* W, 16 <= W <= 4096 */
+    int32_t height;        /* H, 16 <= H <= 4096 */
+    int32_t max_disp;      /* D, disparities 0..D-1; D in {64, 128, 256} */
+    int32_t census_w;      /* odd census window width  (<= 15) */
+    int32_t census_h;      /* odd census window height (<= 15);
+                              (census_w * census_h - 1) / 2 <= 32 bits */
+    int32_t num_paths;     /* 4 (horizontal + vertical) or 8 (+ diagonals),
+                              Sec. III; 1 = left-to-right only (debug) */
+    int32_t p1, p2;        /* SGM penalties, Eq. 1-2 (Tab. II: 10, 120) */
+    int32_t q1, q2;        /* DDC penalties, Eq. 4 (Tab. II: 5, 160), q1 <= q2 */
+    int32_t alpha_num;     /* alpha = alpha_num / alpha_den (Tab. II: 7/10) */
+    int32_t alpha_den;
+    int32_t blend_mode;    /* 0: Eq. 4 at every pixel, DDC = 0 without prior
+                              (cost (1-alpha) H); 1: cost H at full weight
+                              where there is no prior */
+    int32_t semidense;     /* 0 = DSGM, 1 = SDSGM (Tab. I) */
+    int32_t ts, rs;        /* semidensification threshold / window radius,
+                              Eq. 5 (Tab. II: 2, 6); 0 <= rs <= 15 */
+    int32_t tc, rc;        /* consistency threshold / window radius, Eq. 6
+                              (Tab. II: 2, 20); 0 <= rc <= 31 */
+    int32_t check_mode;    /* 0 none, 1 stereo only, 2 LiDAR only,
+                              3 stereo OR LiDAR (Eq. 6; Tab. V variants) */
+    int32_t check_impl;    /* 0: plain right-view pass (only value accepted) */
+    int32_t subpixel;      /* 1: parabola fit (Sec. III end), 0: integer */
+    int32_t batch;         /* max frames per sldf_run_batch call (>= 1) */
+} sldf_params;
+
+/* Optional debug taps: device pointers, any may be NULL.  Written for frame
+   0 of each run.  Dense layouts, row pitch = width:
+     census_l, census_r  uint32 [H][W]
+     prior               int16  [H][W]   D-hat (SDSGM) or D-bar (DSGM)
+     cost_sum            uint16 [H][W][D] aggregated left cost S (Eq. 3 sum)
+     dstar               int16  [H][W]   integer left disparity d*
+     dright              int16  [H][W]   right-view disparity d'
+     dsub                float  [H][W]   subpixel d* before the check */
+typedef struct {
+    uint32_t* census_l;
+    uint32_t* census_r;
+    int16_t* prior;
+    uint16_t* cost_sum;
+    int16_t* dstar;
+    int16_t* dright;
+    float* dsub;
+} sldf_taps;
+
+typedef struct sldf_ctx sldf_ctx;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* sldf_status_string(sldf_status s);
+
+/* ABI version of the loaded library (SLDF_ABI_VERSION). */
+int32_t sldf_abi_version(void);
+
+/* Fill *p with Tab. II parameters for a 1242x375, D=128, 9x7 census, 8-path
+   SDSGM frame with the stereo-LiDAR check.  p must be non-NULL. */
+void sldf_params_default(sldf_params* p);
+
+/* Validate p (shape ranges, odd census window, D, num_paths, q1 <= q2,
+   alpha in [0, 1], the 16-bit bound
+     num_paths * (C'max + P2') < 65536 and C'max + P1' + 2 P2' < 65536,
+   with C'max the largest joint cost) and return the exact device workspace
+   size for p->batch frames in *bytes.  Host only.
+   Errors: EINVAL, ESHAPE, EOVERFLOW. */
+sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes);
+
+/* Create a context on the current HIP device.  dev_workspace: caller-owned
+   device buffer of at least sldf_workspace_size() bytes, 256-byte aligned,
+   which must outlive the context.  *out receives a host-allocated handle.
+   Errors: as sldf_workspace_size, EALIGN (workspace), ENOMEM (ws_bytes too
+   small or host allocation failed), EDEVICE (no HIP device). */
+sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_bytes,
+                        sldf_ctx** out);
+
+/* Release the handle (not the workspace).  NULL is accepted.  The caller
+   must have synchronised the stream of the last run first. */
+sldf_status sldf_destroy(sldf_ctx* ctx);
+
+/* Set the debug taps written by subsequent runs (copied; NULL clears). */
+sldf_status sldf_set_taps(sldf_ctx* ctx, const sldf_taps* taps);
+
+/* Process one frame (the whole method, Fig. 1 flow).  All pointers device:
+     left, right  uint8 [H][img_pitch], 16-byte aligned, img_pitch % 16 == 0
+     lidar        int16 [H][lidar_pitch], D-bar: 0..D-1 or -1 (= invalid), as
+                  written by sldf_lidar_quantize; other values are outside the
+                  contract (memory-safe, result unspecified)
+     disp_out     float [H][out_pitch]: subpixel disparity, -1.0f if invalid
+     valid_out    uint8 [H][out_pitch]: 1 = consistent (Eq. 6), 0 = invalid
+   Enqueue-only on hip_stream.  Errors: EINVAL (NULL pointer / pitch < W),
+   EALIGN, EDEVICE (launch failure). */
+sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
+                     int32_t img_pitch, const int16_t* lidar, int32_t lidar_pitch,
+                     float* disp_out, uint8_t* valid_out, int32_t out_pitch,
+                     void* hip_stream);
+
+/* Process n_frames (1 <= n_frames <= p.batch) frames of the context's shape
+   in one pass; frame i of each array starts at base + i * (its frame stride,
+   in elements; image strides must keep 16-byte alignment).  Same layouts and
+   errors as sldf_run. */
+sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
+                           const uint8_t* right, int32_t img_pitch,
+                           int64_t img_frame_stride, const int16_t* lidar,
+                           int32_t lidar_pitch, int64_t lidar_frame_stride,
+                           float* disp_out, uint8_t* valid_out, int32_t out_pitch,
+                           int64_t out_frame_stride, void* hip_stream);
+
+/* Ingest: quantise projected LiDAR disparities to D-bar on the device.
+   in float [H][in_pitch] (NaN or negative = no return), out int16
+   [H][out_pitch]: round to nearest, ties to even; NaN, negative and values
+   rounding to >= max_disp become -1.  Errors: EINVAL, EDEVICE. */
+sldf_status sldf_lidar_quantize(const float* in, int32_t width, int32_t height,
+                                int32_t in_pitch, int32_t max_disp, int16_t* out,
+                                int32_t out_pitch, void* hip_stream);
+
+/* Stage timing with HIP events recorded on the run's stream (for roofline
+   measurements inside a timed region).  sldf_timing_enable(ctx, n) creates
+   events for up to n runs (host-side HIP events, no device memory) and
+   starts recording; n = 0 stops and frees them.  Stages:
+     0 census, 1 semidensification, 2 SGM path passes (all directions, both
+     views), 3 consistency check.
+   sldf_timing_read waits for the recorded events, writes the summed
+   milliseconds per stage into ms[4] and the number of kernel launches per
+   stage into launches[4] (host arrays), and resets the counters.
+   Errors: EINVAL, ESTATE (not enabled / more runs than events), EDEVICE. */
+#define SLDF_NUM_STAGES 4
+sldf_status sldf_timing_enable(sldf_ctx* ctx, int32_t max_runs);
+sldf_status sldf_timing_read(sldf_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLDF_H */

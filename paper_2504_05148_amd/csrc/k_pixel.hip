@@ -1,0 +1,233 @@
+// Per-pixel kernels: LiDAR ingest, census transform, semidensification and
+// the stereo-LiDAR consistency check.
+#include "sldf_internal.h"
+
+namespace sldf {
+
+// ---------------------------------------------------------------------------
+// Ingest: real LiDAR disparities -> D-bar (values in N or invalid, Sec. IV).
+// Round to nearest, ties to even; NaN, negative and >= D become -1.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void quantize_kernel(const float* in, int W, int H,
+                                                       int in_pitch, int D, int16_t* out,
+                                                       int out_pitch)
+{
+    int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    float v = in[(int64_t)y * in_pitch + x];
+    int16_t q = -1;
+    if (v >= 0.0f) {                    // false for NaN
+        float r = __builtin_rintf(v);   // current rounding mode: nearest even
+        if (r < (float)D) q = (int16_t)r;
+    }
+    out[(int64_t)y * out_pitch + x] = q;
+}
+
+hipError_t launch_quantize(const float* in, int W, int H, int in_pitch, int D,
+                           int16_t* out, int out_pitch, hipStream_t s)
+{
+    dim3 grid((W + 63) / 64, (H + 3) / 4);
+    hipLaunchKernelGGL(quantize_kernel, grid, dim3(256), 0, s, in, W, H, in_pitch, D, out,
+                       out_pitch);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Census transform (Sec. IV-A: Hamming distance of census-transformed images,
+// centre-symmetric variant).  Bit k of the code is [I(p+o_k) > I(p-o_k)] for
+// the first n = (w h - 1) / 2 window offsets in raster order; 0 where the
+// window leaves the image.
+//
+// Tile: 64 x 16 output pixels per 256-thread block, both images of every
+// frame in one launch (blockIdx.z = 2 * frame + view).  Image rows are
+// staged in LDS with 16-byte (128-bit) coalesced loads: each tile row spans
+// [x0 - 16, x0 + 80), 16-byte aligned because the pitch is a multiple of 16.
+// ---------------------------------------------------------------------------
+constexpr int kCensusTW = 64, kCensusTH = 16, kCensusMaxR = 7;
+constexpr int kCensusLW = kCensusTW + 32;
+constexpr int kCensusLH = kCensusTH + 2 * kCensusMaxR;
+
+template <int CWT, int CHT>
+__global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
+{
+    const int cw = CWT ? CWT : a.cw, ch = CHT ? CHT : a.ch;
+    const int rx = (cw - 1) / 2, ry = (ch - 1) / 2, n = (cw * ch - 1) / 2;
+    __shared__ __align__(16) uint8_t tile[kCensusLH][kCensusLW];
+    const int view = blockIdx.z & 1, frame = blockIdx.z >> 1;
+    const uint8_t* img = (view ? a.right : a.left) + (int64_t)frame * a.img_fstride;
+    const int x0 = blockIdx.x * kCensusTW, y0 = blockIdx.y * kCensusTH;
+    const int lh = kCensusTH + 2 * ry;
+    constexpr int chunks = kCensusLW / 16;
+    for (int c = threadIdx.x; c < lh * chunks; c += 256) {
+        int r = c / chunks, cc = c - r * chunks;
+        int gy = y0 - ry + r, gx = x0 - 16 + cc * 16;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.pitch)
+            v = *reinterpret_cast<const uint4*>(img + (int64_t)gy * a.pitch + gx);
+        *reinterpret_cast<uint4*>(&tile[r][cc * 16]) = v;
+    }
+    __syncthreads();
+    uint32_t* out = (view ? a.out_r : a.out_l) + (int64_t)frame * a.px_stride;
+    const int lx = threadIdx.x & 63;
+    for (int ty = threadIdx.x >> 6; ty < kCensusTH; ty += 4) {
+        const int x = x0 + lx, y = y0 + ty;
+        if (x >= a.W || y >= a.H) continue;
+        uint32_t code = 0;
+        if (x >= rx && x < a.W - rx && y >= ry && y < a.H - ry) {
+            const int cy = ry + ty, cx = 16 + lx;
+            int k = 0;
+#pragma unroll
+            for (int dy = -ry; dy <= ry; ++dy) {
+#pragma unroll
+                for (int dx = -rx; dx <= rx; ++dx) {
+                    if (k < n) {
+                        uint32_t p = tile[cy + dy][cx + dx];
+                        uint32_t q = tile[cy - dy][cx - dx];
+                        code |= (uint32_t)(p > q) << k;
+                    }
+                    ++k;
+                }
+            }
+        }
+        out[(int64_t)y * a.W + x] = code;
+    }
+}
+
+hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s)
+{
+    dim3 grid((a.W + kCensusTW - 1) / kCensusTW, (a.H + kCensusTH - 1) / kCensusTH,
+              2 * nframes);
+    if (a.cw == 9 && a.ch == 7)
+        hipLaunchKernelGGL((census_kernel<9, 7>), grid, dim3(256), 0, s, a);
+    else if (a.cw == 5 && a.ch == 5)
+        hipLaunchKernelGGL((census_kernel<5, 5>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((census_kernel<0, 0>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Semidensification, Eq. 5 (Sec. IV-B).  For every pixel p: among the valid
+// sparse disparities in the (2 rs + 1)^2 window (clipped), take the one with
+// the smallest Hamming cost H(p, d) (ties -> smallest d); keep it if that
+// cost is below Ts, otherwise keep the sparse value of p.
+// Block: 16 x 16 pixels; the LiDAR window tile is staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kSemiT = 16, kSemiMaxR = 15, kSemiLT = kSemiT + 2 * kSemiMaxR;
+
+__global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
+{
+    __shared__ int16_t tile[kSemiLT][kSemiLT];
+    const int frame = blockIdx.z;
+    const int16_t* lid = a.lidar + (int64_t)frame * a.lidar_fstride;
+    const int rs = a.rs, lt = kSemiT + 2 * rs;
+    const int x0 = blockIdx.x * kSemiT, y0 = blockIdx.y * kSemiT;
+    for (int i = threadIdx.x; i < lt * lt; i += 256) {
+        int r = i / lt, c = i - r * lt;
+        int gy = y0 - rs + r, gx = x0 - rs + c;
+        int16_t v = -1;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = lid[(int64_t)gy * a.lidar_pitch + gx];
+        tile[r][c] = v;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= a.W || y >= a.H) return;
+    const uint32_t* cl = a.census_l + (int64_t)frame * a.px_stride;
+    const uint32_t* cr_row = a.census_r + (int64_t)frame * a.px_stride + (int64_t)y * a.W;
+    const uint32_t c = cl[(int64_t)y * a.W + x];
+    uint32_t best = 0xffffffffu;   // (H << 16) | d, lexicographic minimum
+    for (int r = 0; r <= 2 * rs; ++r) {
+        for (int q = 0; q <= 2 * rs; ++q) {
+            int d = tile[ty + r][tx + q];
+            if (d < 0) continue;
+            int xm = x - d;
+            uint32_t h = xm >= 0 ? (uint32_t)__builtin_popcount(c ^ cr_row[xm]) : (uint32_t)a.n;
+            uint32_t key = (h << 16) | (uint32_t)d;
+            best = key < best ? key : best;
+        }
+    }
+    int16_t outv = lid[(int64_t)y * a.lidar_pitch + x];
+    if ((best >> 16) < (uint32_t)a.ts) outv = (int16_t)(best & 0xffffu);
+    a.out[(int64_t)frame * a.px_stride + (int64_t)y * a.W + x] = outv;
+}
+
+hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s)
+{
+    dim3 grid((a.W + kSemiT - 1) / kSemiT, (a.H + kSemiT - 1) / kSemiT, nframes);
+    hipLaunchKernelGGL(semidense_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stereo-LiDAR consistency check, Eq. 6 (Sec. IV-C).  A pixel with integer
+// disparity d keeps its (subpixel) disparity if
+//   stereo: the matched right pixel (x - d, y) exists and |d - d'| <= 1, or
+//   LiDAR:  some valid raw sparse value in the (2 rc + 1)^2 window (clipped)
+//           is within Tc of d;
+// mode selects stereo only (1), LiDAR only (2), both (3) or no check (0).
+// Block: 32 x 8 pixels; the LiDAR window tile is staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kChkTW = 32, kChkTH = 8, kChkMaxR = 31;
+constexpr int kChkLW = kChkTW + 2 * kChkMaxR, kChkLH = kChkTH + 2 * kChkMaxR;
+
+__global__ __launch_bounds__(256) void check_kernel(CheckArgs a)
+{
+    __shared__ int16_t tile[kChkLH][kChkLW];
+    const int frame = blockIdx.z;
+    const int rc = a.rc;
+    const int x0 = blockIdx.x * kChkTW, y0 = blockIdx.y * kChkTH;
+    const bool use_lidar = (a.mode & 2) != 0;
+    if (use_lidar) {
+        const int16_t* lid = a.lidar + (int64_t)frame * a.lidar_fstride;
+        const int lw = kChkTW + 2 * rc, lh = kChkTH + 2 * rc;
+        for (int i = threadIdx.x; i < lw * lh; i += 256) {
+            int r = i / lw, c = i - r * lw;
+            int gy = y0 - rc + r, gx = x0 - rc + c;
+            int16_t v = -1;
+            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                v = lid[(int64_t)gy * a.lidar_pitch + gx];
+            tile[r][c] = v;
+        }
+        __syncthreads();
+    }
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= a.W || y >= a.H) return;
+    const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
+    const int d = a.dstar[p];
+    bool valid = a.mode == 0;
+    if (a.mode & 1) {
+        int xm = x - d;
+        if (xm >= 0) {
+            int dr = a.dright[p - x + xm];
+            int diff = d - dr;
+            valid = diff >= -1 && diff <= 1;
+        }
+    }
+    if (use_lidar && !valid) {
+        for (int r = 0; r <= 2 * rc && !valid; ++r) {
+            for (int q = 0; q <= 2 * rc; ++q) {
+                int v = tile[ty + r][tx + q];
+                int diff = d - v;
+                if (v >= 0 && diff >= -a.tc && diff <= a.tc) {
+                    valid = true;
+                    break;
+                }
+            }
+        }
+    }
+    const int64_t o = (int64_t)frame * a.out_fstride + (int64_t)y * a.out_pitch + x;
+    a.valid_out[o] = valid ? 1 : 0;
+    a.disp_out[o] = valid ? a.dsub[p] : -1.0f;
+}
+
+hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s)
+{
+    dim3 grid((a.W + kChkTW - 1) / kChkTW, (a.H + kChkTH - 1) / kChkTH, nframes);
+    hipLaunchKernelGGL(check_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sldf

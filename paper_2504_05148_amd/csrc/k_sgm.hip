@@ -1,0 +1,354 @@
+// SGM path aggregation with the joint census + DDC cost fused in, and the
+// winner-takes-all + subpixel step fused into the last path.
+//
+// One launch handles one path direction r = (dx, dy) for both views and all
+// frames of a batch.  Every line of that direction (a row, a column or a
+// diagonal) is an independent recurrence (Sec. III, Eq. 2):
+//   L_r(p,d) = C(p,d) + min(L_r(p-r,d), L_r(p-r,d+-1) + P1, m + P2) - m,
+//   m = min_k L_r(p-r,k),   L_r = C at the start of the line.
+// A line is owned by a group of G = D / 8 lanes of one wavefront; lane g of
+// the group holds disparities [8g, 8g + 8) as four packed 2 x u16 registers,
+// so one VALU instruction (v_pk_*_u16) advances two disparities.  The d +- 1
+// neighbours across lane boundaries come from one wave_shr / wave_shl DPP
+// move each, and the running minimum over d is an in-lane packed minimum
+// followed by a DPP butterfly inside the group (quad_perm, half-row mirror,
+// row mirror and, for 32-lane groups, a permlane16 swap).  No MFMA: the path
+// is integer min-plus arithmetic.
+//
+// The joint cost C'(p,d) = (den - num) H(p,d) + num DDC(d, prior_p)
+// (Sec. IV-A, Eq. 4, scaled by den = alpha denominator so every term is an
+// integer) is rebuilt at every step from the census codes (xor + popcount)
+// and a per-block LDS table of the DDC pattern, so the cost volume is never
+// materialised.  The aggregated sum S = sum_r L_r (Eq. 3) is kept as u16 in
+// HBM: the first direction stores it, the middle ones add into it, and the
+// last one adds its own L_r in registers and takes the WTA (ties -> smallest
+// d) and the parabola fit through S(d*-1), S(d*), S(d*+1) directly.
+// All values are bounded by the 16-bit limit that the host checks, so the
+// modular u16 arithmetic is exact.
+#include "sldf_internal.h"
+
+namespace sldf {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ u16x2 v2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t u1(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
+{
+    return u1(__builtin_elementwise_min(v2(a), v2(b)));
+}
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) { return u1(v2(a) + v2(b)); }
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) { return u1(v2(a) - v2(b)); }
+__device__ __forceinline__ uint32_t pk_mad(uint32_t a, uint32_t b, uint32_t c)
+{
+    return u1(v2(a) * v2(b) + v2(c));
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int kQuadXor1 = 0xB1;        // quad_perm:[1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;        // quad_perm:[2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kWaveShr1 = 0x138;       // lane i <- lane i-1
+constexpr int kWaveShl1 = 0x130;       // lane i <- lane i+1
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0u, v, CTRL, 0xf, 0xf, true);
+}
+
+// Minimum over the G lanes of a group, broadcast to all of them.
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v)
+{
+    v = min(v, dpp<kQuadXor1>(v));
+    v = min(v, dpp<kQuadXor2>(v));
+    v = min(v, dpp<kRowHalfMirror>(v));
+    if (G >= 16) v = min(v, dpp<kRowMirror>(v));
+    if (G >= 32) {
+        auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = min(sw[0], sw[1]);
+    }
+    return v;
+}
+
+__device__ __forceinline__ void line_start(int line, int W, int H, int dx, int dy, int& x,
+                                           int& y, int& len)
+{
+    if (dy == 0) {
+        y = line;
+        x = dx > 0 ? 0 : W - 1;
+        len = W;
+    } else if (dx == 0) {
+        x = line;
+        y = dy > 0 ? 0 : H - 1;
+        len = H;
+    } else {
+        if (line < W) {
+            x = line;
+            y = dy > 0 ? 0 : H - 1;
+        } else {
+            int k = line - W + 1;
+            x = dx > 0 ? 0 : W - 1;
+            y = dy > 0 ? k : H - 1 - k;
+        }
+        int nx = dx > 0 ? W - x : x + 1;
+        int ny = dy > 0 ? H - y : y + 1;
+        len = nx < ny ? nx : ny;
+    }
+}
+
+// Inputs of one step (one pixel of the line) for one lane.
+struct StepIn {
+    uint32_t cb;        // census of the base pixel
+    uint32_t cm[8];     // census of the matching pixels for the lane's 8 d
+    int32_t e;          // prior disparity (-1 = none)
+    uint4 s;            // partial S of the lane's 8 d (middle / last passes)
+};
+
+template <int D, int VIEW, bool LOAD_S>
+__device__ __forceinline__ void load_step(const SgmArgs& a, const uint32_t* cbase,
+                                          const uint32_t* cmatch, const int16_t* prior,
+                                          const uint16_t* S, int x, int y, int d0,
+                                          uint32_t maskn, StepIn& st)
+{
+    const int64_t row = (int64_t)y * a.W;
+    st.cb = cbase[row + x];
+    const uint32_t* mrow = cmatch + row;
+    if (VIEW == 0) {
+        // matching pixels x - d for d = d0 .. d0+7 (descending addresses)
+        const int base = x - d0 - 7;
+        if (base >= 0) {
+            u32x4a4 lo = *reinterpret_cast<const u32x4a4*>(mrow + base);
+            u32x4a4 hi = *reinterpret_cast<const u32x4a4*>(mrow + base + 4);
+            st.cm[0] = hi.w; st.cm[1] = hi.z; st.cm[2] = hi.y; st.cm[3] = hi.x;
+            st.cm[4] = lo.w; st.cm[5] = lo.z; st.cm[6] = lo.y; st.cm[7] = lo.x;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                int xm = x - d0 - j;
+                st.cm[j] = xm >= 0 ? mrow[xm] : (st.cb ^ maskn);
+            }
+        }
+        st.e = prior ? (int32_t)prior[(int64_t)y * a.prior_pitch + x] : -1;
+    } else {
+        // matching pixels x + d (ascending addresses)
+        const int base = x + d0;
+        if (base + 7 < a.W) {
+            u32x4a4 lo = *reinterpret_cast<const u32x4a4*>(mrow + base);
+            u32x4a4 hi = *reinterpret_cast<const u32x4a4*>(mrow + base + 4);
+            st.cm[0] = lo.x; st.cm[1] = lo.y; st.cm[2] = lo.z; st.cm[3] = lo.w;
+            st.cm[4] = hi.x; st.cm[5] = hi.y; st.cm[6] = hi.z; st.cm[7] = hi.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                int xm = base + j;
+                st.cm[j] = xm < a.W ? mrow[xm] : (st.cb ^ maskn);
+            }
+        }
+        st.e = -1;
+    }
+    if (LOAD_S) st.s = *reinterpret_cast<const uint4*>(S + (row + x) * D + d0);
+}
+
+template <int G, int MODE, int VIEW>
+__device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, int line,
+                                         int g, int frame)
+{
+    constexpr int D = G * 8;
+    constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
+    constexpr bool kWta = MODE == kLast || MODE == kSingle;
+    int x, y, len;
+    line_start(line, a.W, a.H, a.dx, a.dy, x, y, len);
+    const int d0 = g * 8;
+    const uint32_t* cbase = a.cbase[VIEW] + (int64_t)frame * a.px_stride;
+    const uint32_t* cmatch = a.cmatch[VIEW] + (int64_t)frame * a.px_stride;
+    const int16_t* prior = VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
+    uint16_t* S = a.S[VIEW] + (int64_t)frame * a.S_stride;
+    const uint32_t maskn = a.n >= 32 ? 0xffffffffu : ((1u << a.n) - 1u);
+    const uint32_t p1x2 = a.p1s * 0x10001u;
+    const bool gfirst = g == 0, glast = g == G - 1;
+
+    uint32_t L[4] = {0, 0, 0, 0};
+    uint32_t m = 0;
+    StepIn cur, nxt;
+    load_step<D, VIEW, kLoadS>(a, cbase, cmatch, prior, S, x, y, d0, maskn, cur);
+    for (int t = 0; t < len; ++t) {
+        const int xn = x + a.dx, yn = y + a.dy;
+        if (t + 1 < len) load_step<D, VIEW, kLoadS>(a, cbase, cmatch, prior, S, xn, yn, d0, maskn, nxt);
+
+        // ---- joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4, scaled) ----
+        uint32_t h[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(cur.cb ^ cur.cm[j]);
+        uint32_t C[4];
+        // values outside [0, D) carry no prior (the ABI only admits -1 there)
+        const bool has = (unsigned)cur.e < (unsigned)D;
+        const uint32_t mulh = (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u;
+        if (VIEW == 0 && has) {
+            // DDC pattern entry for disparity d sits at index d - e + D
+            const int s = d0 - cur.e + D;
+            const uint32_t* pp = (s & 1) ? pat + (D + 8) + ((s - 1) >> 1) : pat + (s >> 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pp[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, 0u);
+        }
+
+        // ---- path recurrence, Eq. 2 ----
+        if (t == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) L[i] = C[i];
+        } else {
+            uint32_t pv = dpp<kWaveShr1>(L[3]);   // hi half: cell d0-1
+            uint32_t nx = dpp<kWaveShl1>(L[0]);   // lo half: cell d0+8
+            // ends of the disparity range: reuse the cell itself, which is
+            // already a candidate of the minimum (= leaving the term out)
+            pv = gfirst ? (L[0] << 16) : pv;
+            nx = glast ? (L[3] >> 16) : nx;
+            uint32_t Dm[5];
+            Dm[0] = __builtin_amdgcn_alignbit(L[0], pv, 16);
+            Dm[1] = __builtin_amdgcn_alignbit(L[1], L[0], 16);
+            Dm[2] = __builtin_amdgcn_alignbit(L[2], L[1], 16);
+            Dm[3] = __builtin_amdgcn_alignbit(L[3], L[2], 16);
+            Dm[4] = __builtin_amdgcn_alignbit(nx, L[3], 16);
+            const uint32_t mp2 = (m + a.p2s) * 0x10001u;
+            const uint32_t mm = m * 0x10001u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
+                uint32_t best = pk_min(pk_min(L[i], nb), mp2);
+                L[i] = pk_add(best, pk_sub(C[i], mm));
+            }
+        }
+        {
+            uint32_t mn = pk_min(pk_min(L[0], L[1]), pk_min(L[2], L[3]));
+            m = group_min<G>(min(mn & 0xffffu, mn >> 16));
+        }
+
+        // ---- aggregated sum S (Eq. 3) ----
+        const int64_t cell = ((int64_t)y * a.W + x) * D + d0;
+        if (MODE == kFirst) {
+            *reinterpret_cast<uint4*>(S + cell) = make_uint4(L[0], L[1], L[2], L[3]);
+        } else if (MODE == kMiddle) {
+            uint4 o = make_uint4(pk_add(cur.s.x, L[0]), pk_add(cur.s.y, L[1]),
+                                 pk_add(cur.s.z, L[2]), pk_add(cur.s.w, L[3]));
+            *reinterpret_cast<uint4*>(S + cell) = o;
+        } else {
+            uint32_t St[4];
+            if (MODE == kLast) {
+                St[0] = pk_add(cur.s.x, L[0]); St[1] = pk_add(cur.s.y, L[1]);
+                St[2] = pk_add(cur.s.z, L[2]); St[3] = pk_add(cur.s.w, L[3]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) St[i] = L[i];
+            }
+            if (a.store_sum)
+                *reinterpret_cast<uint4*>(S + cell) = make_uint4(St[0], St[1], St[2], St[3]);
+            // ---- WTA, Eq. 3: lexicographic minimum of (S, d) ----
+            uint32_t best = 0xffffffffu;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t k0 = ((St[i] & 0xffffu) << 9) | (uint32_t)(d0 + 2 * i);
+                uint32_t k1 = ((St[i] >> 16) << 9) | (uint32_t)(d0 + 2 * i + 1);
+                best = min(best, min(k0, k1));
+            }
+            best = group_min<G>(best);
+            const int db = (int)(best & 511u);
+            uint32_t spv = dpp<kWaveShr1>(St[3]);
+            uint32_t snx = dpp<kWaveShl1>(St[0]);
+            if (db >= d0 && db < d0 + 8) {
+                const int64_t px = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
+                a.wta[VIEW][px] = (int16_t)db;
+                if (VIEW == 0) {
+                    // cells d0-1 .. d0+8 of S
+                    uint32_t c[10];
+                    c[0] = spv >> 16;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        c[1 + 2 * i] = St[i] & 0xffffu;
+                        c[2 + 2 * i] = St[i] >> 16;
+                    }
+                    c[9] = snx & 0xffffu;
+                    const int j = db - d0 + 1;
+                    uint32_t A = 0, B = 0, Cc = 0;
+#pragma unroll
+                    for (int k = 1; k <= 8; ++k) {
+                        if (k == j) {
+                            A = c[k - 1];
+                            B = c[k];
+                            Cc = c[k + 1];
+                        }
+                    }
+                    float v = (float)db;
+                    if (a.subpixel && db > 0 && db < D - 1) {
+                        int den = (int)A - 2 * (int)B + (int)Cc;
+                        if (den > 0) v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
+                    }
+                    a.dsub[px] = v;
+                }
+            }
+        }
+        x = xn;
+        y = yn;
+        cur = nxt;
+    }
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
+{
+    constexpr int D = G * 8;
+    // DDC pattern (Eq. 4 term divided out of the cost: 0 at the prior, Q1 at
+    // +-1, Q2 beyond), as pairs of u16 starting at even (first half) and odd
+    // (second half) entries of P[k] = ddc(k - D), k in [0, 2D + 16).
+    __shared__ uint32_t pat[2 * (D + 8)];
+    for (int i = threadIdx.x; i < 2 * (D + 8); i += 256) {
+        const int half = i >= D + 8;
+        const int k0 = 2 * (i - half * (D + 8)) + half;
+        uint32_t v[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            int diff = k0 + j - D;
+            diff = diff < 0 ? -diff : diff;
+            v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+        }
+        pat[i] = v[0] | (v[1] << 16);
+    }
+    __syncthreads();
+    const int g = threadIdx.x % G;
+    const int line = blockIdx.x * (256 / G) + threadIdx.x / G;
+    if (line >= a.nlines) return;
+    if (blockIdx.y == 0)
+        run_line<G, MODE, 0>(a, pat, line, g, blockIdx.z);
+    else
+        run_line<G, MODE, 1>(a, pat, line, g, blockIdx.z);
+}
+
+template <int G>
+static void launch_g(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
+{
+    switch (mode) {
+    case kFirst: hipLaunchKernelGGL((sgm_dir_kernel<G, kFirst>), grid, dim3(256), 0, s, a); break;
+    case kMiddle: hipLaunchKernelGGL((sgm_dir_kernel<G, kMiddle>), grid, dim3(256), 0, s, a); break;
+    case kLast: hipLaunchKernelGGL((sgm_dir_kernel<G, kLast>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((sgm_dir_kernel<G, kSingle>), grid, dim3(256), 0, s, a); break;
+    }
+}
+
+hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+                          hipStream_t s)
+{
+    const int G = D / 8;
+    const int lines_per_block = 256 / G;
+    dim3 grid((a.nlines + lines_per_block - 1) / lines_per_block, nviews, nframes);
+    if (G == 8) launch_g<8>(a, mode, grid, s);
+    else if (G == 16) launch_g<16>(a, mode, grid, s);
+    else launch_g<32>(a, mode, grid, s);
+    return hipGetLastError();
+}
+
+}  // namespace sldf

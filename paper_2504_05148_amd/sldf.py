@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libsldf.so (include/sldf.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory (tensors) and the HIP stream
+(``torch.cuda.current_stream().cuda_stream``).  If the library is missing,
+every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsldf.so")
+
+OK, EINVAL, ESHAPE, EALIGN, EOVERFLOW, ENOMEM, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+
+_PARAM_FIELDS = ("struct_size", "width", "height", "max_disp", "census_w", "census_h",
+                 "num_paths", "p1", "p2", "q1", "q2", "alpha_num", "alpha_den",
+                 "blend_mode", "semidense", "ts", "rs", "tc", "rc", "check_mode",
+                 "check_impl", "subpixel", "batch")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in _PARAM_FIELDS]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in _PARAM_FIELDS}
+
+
+class Taps(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in
+                ("census_l", "census_r", "prior", "cost_sum", "dstar", "dright", "dsub")]
+
+
+class SldfError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_lib = None
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+
+
+def lib():
+    """Load libsldf.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libsldf.so not built ({LIB_PATH}); run "
+                               "paper_2504_05148_amd.build.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        L.sldf_status_string.restype = ctypes.c_char_p
+        L.sldf_status_string.argtypes = [ctypes.c_int]
+        L.sldf_abi_version.restype = _i32
+        L.sldf_params_default.argtypes = [ctypes.POINTER(Params)]
+        L.sldf_params_default.restype = None
+        L.sldf_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(_sz)]
+        L.sldf_create.argtypes = [ctypes.POINTER(Params), _vp, _sz, ctypes.POINTER(_vp)]
+        L.sldf_destroy.argtypes = [_vp]
+        L.sldf_set_taps.argtypes = [_vp, ctypes.POINTER(Taps)]
+        L.sldf_run.argtypes = [_vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _i32, _vp]
+        L.sldf_run_batch.argtypes = [_vp, _i32, _vp, _vp, _i32, _i64, _vp, _i32, _i64,
+                                     _vp, _vp, _i32, _i64, _vp]
+        L.sldf_lidar_quantize.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]
+        L.sldf_timing_enable.argtypes = [_vp, _i32]
+        L.sldf_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
+        for f in ("sldf_workspace_size", "sldf_create", "sldf_destroy", "sldf_set_taps",
+                  "sldf_run", "sldf_run_batch", "sldf_lidar_quantize",
+                  "sldf_timing_enable", "sldf_timing_read"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().sldf_status_string(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise SldfError(status, what)
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().sldf_params_default(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k not in _PARAM_FIELDS:
+            raise KeyError(k)
+        setattr(p, k, int(v))
+    return p
+
+
+def workspace_size(p: Params) -> int:
+    n = _sz()
+    _check(lib().sldf_workspace_size(ctypes.byref(p), ctypes.byref(n)), "sldf_workspace_size")
+    return int(n.value)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return int(t.data_ptr())
+
+
+def device_image(img, device="cuda") -> torch.Tensor:
+    """uint8 [H, W] -> device tensor [H, W] whose rows sit on a 16-byte
+    pitch (a view into an [H, pitch] buffer)."""
+    t = torch.as_tensor(img, dtype=torch.uint8)
+    H, W = t.shape
+    pitch = (W + 15) // 16 * 16
+    buf = torch.zeros((H, pitch), dtype=torch.uint8, device=device)
+    buf[:, :W].copy_(t.to(device))
+    return buf[:, :W]
+
+
+def device_images(imgs, device="cuda") -> torch.Tensor:
+    """Stack of uint8 [F, H, W] on a 16-byte row pitch (a view)."""
+    t = torch.as_tensor(imgs, dtype=torch.uint8)
+    F, H, W = t.shape
+    pitch = (W + 15) // 16 * 16
+    buf = torch.zeros((F, H, pitch), dtype=torch.uint8, device=device)
+    buf[:, :, :W].copy_(t.to(device))
+    return buf[:, :, :W]
+
+
+def quantize_lidar(lidar: torch.Tensor, max_disp: int, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """float32 [H, W] (NaN = no return) -> int16 D-bar on the device."""
+    assert lidar.dtype == torch.float32 and lidar.is_cuda and lidar.dim() == 2
+    assert lidar.stride(1) == 1
+    H, W = lidar.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int16, device=lidar.device)
+    assert out.stride(1) == 1
+    _check(lib().sldf_lidar_quantize(_ptr(lidar), W, H, lidar.stride(0), max_disp, _ptr(out),
+                                     out.stride(0), _stream_handle(stream)),
+           "sldf_lidar_quantize")
+    return out
+
+
+class Context:
+    """One context per rig / shape: parameters plus a caller-owned device
+    workspace of exactly ``workspace_size(params)`` bytes."""
+
+    def __init__(self, params: Params, device=None):
+        self.params = params
+        self.device = torch.device(device if device is not None else "cuda")
+        self.ws_bytes = workspace_size(params)
+        # 256-byte aligned workspace (the caching allocator aligns to 512)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-_ptr(self.workspace)) % 256
+        self._ws = self.workspace[off:off + self.ws_bytes]
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().sldf_create(ctypes.byref(params), _ptr(self._ws), self.ws_bytes,
+                                     ctypes.byref(h)), "sldf_create")
+        self._h = h
+        self._taps_keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sldf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_taps(self, **tensors):
+        """Debug taps (frame 0): census_l, census_r, prior, cost_sum, dstar,
+        dright, dsub -> device tensors of the documented dtypes."""
+        t = Taps()
+        for k, v in tensors.items():
+            setattr(t, k, _ptr(v) if v is not None else None)
+        self._taps_keep = dict(tensors)
+        _check(lib().sldf_set_taps(self._h, ctypes.byref(t)), "sldf_set_taps")
+
+    STAGES = ("census", "semidense", "sgm", "check")
+
+    def timing_enable(self, max_runs: int):
+        _check(lib().sldf_timing_enable(self._h, int(max_runs)), "sldf_timing_enable")
+
+    def timing_read(self):
+        """{stage: (total_ms, launches)} since the last read (waits on events)."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(lib().sldf_timing_read(self._h, ms, n), "sldf_timing_read")
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.STAGES)}
+
+    def new_outputs(self, n_frames: int | None = None):
+        W, H = self.params.width, self.params.height
+        shape = (H, W) if n_frames is None else (n_frames, H, W)
+        disp = torch.empty(shape, dtype=torch.float32, device=self.device)
+        valid = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        return disp, valid
+
+    def run(self, left, right, lidar, disp=None, valid=None, stream=None):
+        """One frame: left/right uint8 [H, W] (16-byte row pitch), lidar int16
+        [H, W]; returns (disp float32, valid uint8), enqueued on stream."""
+        if disp is None or valid is None:
+            disp, valid = self.new_outputs()
+        for t in (left, right, lidar, disp, valid):
+            assert t.is_cuda and t.stride(-1) == 1
+        assert left.stride(0) == right.stride(0)
+        assert disp.stride(0) == valid.stride(0)
+        _check(lib().sldf_run(self._h, _ptr(left), _ptr(right), left.stride(0), _ptr(lidar),
+                              lidar.stride(0), _ptr(disp), _ptr(valid), disp.stride(0),
+                              _stream_handle(stream)), "sldf_run")
+        return disp, valid
+
+    def run_batch(self, left, right, lidar, disp=None, valid=None, stream=None):
+        """n frames: left/right uint8 [F, H, W], lidar int16 [F, H, W]."""
+        F = left.shape[0]
+        if disp is None or valid is None:
+            disp, valid = self.new_outputs(F)
+        assert left.stride() == right.stride() and disp.stride() == valid.stride()
+        _check(lib().sldf_run_batch(self._h, F, _ptr(left), _ptr(right), left.stride(1),
+                                    left.stride(0), _ptr(lidar), lidar.stride(1),
+                                    lidar.stride(0), _ptr(disp), _ptr(valid), disp.stride(1),
+                                    disp.stride(0), _stream_handle(stream)),
+               "sldf_run_batch")
+        return disp, valid

@@ -1,0 +1,95 @@
+"""The C ABI library loads and exports every symbol include/sldf.h declares;
+host-only entry points (defaults, validation, workspace plan) behave as
+documented.  No GPU work is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2504_05148_amd import sldf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sldf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(sldf_[a-z_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("sldf_create", "sldf_run", "sldf_run_batch", "sldf_workspace_size",
+              "sldf_destroy", "sldf_set_taps", "sldf_lidar_quantize", "sldf_status_string",
+              "sldf_params_default", "sldf_abi_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = sldf.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+
+
+def test_params_default_is_tab2():
+    p = sldf.default_params()
+    assert p.struct_size == ctypes.sizeof(sldf.Params)
+    assert (p.ts, p.rs, p.p1, p.p2, p.q1, p.q2, p.tc, p.rc) == (2, 6, 10, 120, 5, 160, 2, 20)
+    assert (p.alpha_num, p.alpha_den) == (7, 10)
+    assert (p.width, p.height, p.max_disp, p.census_w, p.census_h, p.num_paths) == (
+        1242, 375, 128, 9, 7, 8)
+    assert p.semidense == 1 and p.check_mode == 3 and p.subpixel == 1
+    assert sldf.lib().sldf_abi_version() == 1
+
+
+def test_workspace_size_plan():
+    p = sldf.default_params()
+    n1 = sldf.workspace_size(p)
+    px, cells = 1242 * 375, 1242 * 375 * 128
+    # census x2 (u32), prior, d*, d' (i16), dsub (f32), S left + right (u16)
+    assert n1 >= px * (4 + 4 + 2 + 2 + 2 + 4) + 2 * cells * 2
+    assert n1 < px * (4 + 4 + 2 + 2 + 2 + 4) + 2 * cells * 2 + 8 * 256
+    p.batch = 4
+    assert sldf.workspace_size(p) >= 4 * (n1 - 8 * 256)
+    p = sldf.default_params(check_mode=2)      # no right-view pass: one S volume
+    assert sldf.workspace_size(p) < n1 - cells
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("struct_size", 4, sldf.EINVAL),
+    ("width", 8, sldf.ESHAPE),
+    ("height", 5000, sldf.ESHAPE),
+    ("max_disp", 96, sldf.ESHAPE),
+    ("census_w", 8, sldf.EINVAL),
+    ("census_h", 17, sldf.EINVAL),
+    ("num_paths", 2, sldf.EINVAL),
+    ("q2", 4, sldf.EINVAL),            # Q1 <= Q2 (Sec. IV-A)
+    ("alpha_num", 11, sldf.EINVAL),
+    ("rs", 16, sldf.EINVAL),
+    ("rc", 32, sldf.EINVAL),
+    ("check_mode", 4, sldf.EINVAL),
+    ("check_impl", 1, sldf.EINVAL),
+    ("batch", 0, sldf.EINVAL),
+    ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
+])
+def test_validation(field, value, status):
+    p = sldf.default_params(**{field: value})
+    with pytest.raises(sldf.SldfError) as ei:
+        sldf.workspace_size(p)
+    assert ei.value.status == status
+
+
+def test_overflow_bound_is_tight():
+    # C'max = 3*31 + 7*160 = 1213; 8 * (1213 + 10*P2) < 65536 <=> P2 <= 697
+    assert sldf.workspace_size(sldf.default_params(p2=697)) > 0
+    with pytest.raises(sldf.SldfError):
+        sldf.workspace_size(sldf.default_params(p2=698))
+
+
+def test_status_strings():
+    for s in range(-7, 1):
+        assert sldf.status_string(s)
+    assert sldf.status_string(-99) == "unknown status"

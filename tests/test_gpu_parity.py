@@ -1,0 +1,237 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by
+element on the same seeded inputs: bit-exact for census codes, the prior
+map, the aggregated cost S, integer disparities and masks; the subpixel
+disparity within 1e-4 px (expected bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2504_05148_amd import sldf, synth
+
+pytestmark = pytest.mark.gpu
+
+SUB_TOL = 1e-4
+
+
+def _params(W, H, D, **kw):
+    base = dict(width=W, height=H, max_disp=D)
+    base.update(kw)
+    return base
+
+
+def _oracle_params(p: dict) -> oracle.OracleParams:
+    return oracle.OracleParams(
+        W=p["width"], H=p["height"], D=p["max_disp"], cw=p.get("census_w", 9),
+        ch=p.get("census_h", 7), num_paths=p.get("num_paths", 8), p1=p.get("p1", 10),
+        p2=p.get("p2", 120), q1=p.get("q1", 5), q2=p.get("q2", 160),
+        a=p.get("alpha_num", 7), b=p.get("alpha_den", 10), blend_mode=p.get("blend_mode", 0),
+        semidense=p.get("semidense", 1), ts=p.get("ts", 2), rs=p.get("rs", 6),
+        tc=p.get("tc", 2), rc=p.get("rc", 20), check_mode=p.get("check_mode", 3),
+        subpixel=p.get("subpixel", 1))
+
+
+def run_gpu(frame, pkw, taps=True):
+    p = sldf.default_params(**pkw)
+    W, H, D = p.width, p.height, p.max_disp
+    ctx = sldf.Context(p)
+    left = sldf.device_image(frame["left"])
+    right = sldf.device_image(frame["right"])
+    lid_f = torch.from_numpy(np.ascontiguousarray(frame["lidar"])).cuda()
+    lid_q = sldf.quantize_lidar(lid_f, D)
+    out = {}
+    if taps:
+        dev = "cuda"
+        t = dict(census_l=torch.empty((H, W), dtype=torch.int32, device=dev),
+                 census_r=torch.empty((H, W), dtype=torch.int32, device=dev),
+                 prior=torch.empty((H, W), dtype=torch.int16, device=dev),
+                 cost_sum=torch.empty((H, W, D), dtype=torch.int16, device=dev),
+                 dstar=torch.empty((H, W), dtype=torch.int16, device=dev),
+                 dright=torch.full((H, W), -7, dtype=torch.int16, device=dev),
+                 dsub=torch.empty((H, W), dtype=torch.float32, device=dev))
+        ctx.set_taps(**t)
+    disp, valid = ctx.run(left, right, lid_q)
+    torch.cuda.synchronize()
+    out["disp"] = disp.cpu().numpy()
+    out["valid"] = valid.cpu().numpy()
+    out["lidar_q"] = lid_q.cpu().numpy()
+    if taps:
+        out["census_l"] = t["census_l"].cpu().numpy().view(np.uint32)
+        out["census_r"] = t["census_r"].cpu().numpy().view(np.uint32)
+        out["prior"] = t["prior"].cpu().numpy()
+        out["S"] = t["cost_sum"].cpu().numpy().view(np.uint16)
+        out["dstar"] = t["dstar"].cpu().numpy()
+        out["dright"] = t["dright"].cpu().numpy()
+        out["dsub"] = t["dsub"].cpu().numpy()
+    ctx.close()
+    return out
+
+
+def run_oracle(frame, pkw):
+    op = _oracle_params(sldf.default_params(**pkw).as_dict() | pkw)
+    lid = oracle.quantize_lidar(frame["lidar"], op.D)
+    r = oracle.run(op, frame["left"], frame["right"], lid, taps=True)
+    r["lidar_q"] = lid
+    return r
+
+
+def assert_parity(g, o, pkw, taps=True):
+    assert (g["lidar_q"] == o["lidar_q"]).all(), "lidar quantisation"
+    if taps:
+        assert (g["census_l"] == o["census_l"]).all(), "census left"
+        assert (g["census_r"] == o["census_r"]).all(), "census right"
+        assert (g["prior"] == o["prior"]).all(), "prior map"
+        bad = g["S"].astype(np.int64) != o["S"]
+        assert not bad.any(), f"S mismatch at {np.argwhere(bad)[:5]}"
+        assert (g["dstar"] == o["dstar"]).all(), "d*"
+        if pkw.get("check_mode", 3) in (1, 3):
+            assert (g["dright"] == o["dright"]).all(), "d'"
+        diff = np.abs(g["dsub"] - o["dsub"])
+        assert diff.max() <= SUB_TOL, f"dsub max diff {diff.max()}"
+    assert (g["valid"] == o["valid"]).all(), f"mask mismatch {np.argwhere(g['valid'] != o['valid'])[:5]}"
+    assert (g["disp"][g["valid"] == 0] == -1.0).all()
+    d = np.abs(g["disp"] - o["disp"])
+    assert d.max() <= SUB_TOL, f"disp max diff {d.max()}"
+
+
+SMALL = dict(census_w=5, census_h=5, num_paths=4)
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+@pytest.mark.parametrize("semi", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_small_workload(idx, semi, mode):
+    f = synth.small_frame(idx)
+    pkw = _params(f["W"], f["H"], f["D"], semidense=semi, check_mode=mode, **SMALL)
+    print(f"case small idx={idx} semi={semi} mode={mode}", flush=True)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
+def test_small_bit_exact_subpixel():
+    f = synth.small_frame(2)
+    pkw = _params(f["W"], f["H"], f["D"], **SMALL)
+    g, o = run_gpu(f, pkw), run_oracle(f, pkw)
+    assert (g["dsub"].view(np.uint32) == o["dsub"].view(np.uint32)).all()
+
+
+def test_paper_scale_frame():
+    """1242 x 375, D = 128, 9x7 census, 8 paths, SDSGM, stereo-LiDAR check."""
+    f = synth.kitti_frame(0)
+    pkw = _params(1242, 375, 128)
+    print("case kitti frame 0", flush=True)
+    g, o = run_gpu(f, pkw), run_oracle(f, pkw)
+    assert_parity(g, o, pkw)
+    assert (g["dsub"].view(np.uint32) == o["dsub"].view(np.uint32)).all()
+
+
+def test_paper_scale_dsgm():
+    f = synth.kitti_frame(1)
+    pkw = _params(1242, 375, 128, semidense=0)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
+@pytest.mark.parametrize("W,H,D,paths", [(333, 77, 128, 8), (130, 19, 64, 8), (301, 40, 256, 8),
+                                         (300, 45, 256, 4), (97, 130, 64, 4)])
+def test_ragged_shapes(W, H, D, paths):
+    """Shapes that are not multiples of any tile, every disparity range."""
+    spec = synth.robust_spec(W=W, H=H, D=D, density=0.05, lines=16)
+    f = synth.make_frame(spec, 3, W * 7 + H)
+    pkw = _params(W, H, D, num_paths=paths)
+    print(f"case ragged {W}x{H} D={D} paths={paths}", flush=True)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
+@pytest.mark.parametrize("extra", [
+    dict(blend_mode=1), dict(subpixel=0), dict(num_paths=1), dict(rs=0, rc=0, tc=0),
+    dict(rs=15, rc=31, ts=9), dict(alpha_num=0), dict(alpha_num=10, q1=0, q2=5),
+    dict(census_w=7, census_h=7), dict(census_w=3, census_h=9), dict(p1=0, p2=0),
+])
+def test_parameter_variants(extra):
+    f = synth.small_frame(4)
+    pkw = _params(f["W"], f["H"], f["D"], **SMALL)
+    pkw.update(extra)
+    print(f"case variant {extra}", flush=True)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
+@pytest.mark.parametrize("density", [0.0, 0.3])
+def test_lidar_empty_and_dense(density):
+    f = dict(synth.small_frame(5))
+    rng = np.random.default_rng(5)
+    lid = np.full(f["lidar"].shape, np.nan, np.float32)
+    m = rng.random(lid.shape) < density
+    lid[m] = (f["gt"][m] + rng.normal(0, 0.4, m.sum())).astype(np.float32)
+    f["lidar"] = lid
+    pkw = _params(f["W"], f["H"], f["D"], **SMALL)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
+def test_lidar_quantise_edge_values():
+    vals = np.array([[np.nan, -0.3, 0.4, 2.5, 3.5, 62.5, 63.49, 63.5, 100.0, -np.inf, np.inf,
+                      0.5, 1.5, 127.5, 126.5, 0.0]], np.float32)
+    vals = np.repeat(vals, 3, axis=0)
+    g = sldf.quantize_lidar(torch.from_numpy(vals).cuda(), 64).cpu().numpy()
+    assert (g == oracle.quantize_lidar(vals, 64)).all()
+
+
+def test_batch_matches_single_frames():
+    """run_batch over 3 frames equals three single-frame runs and the oracle."""
+    frames = [synth.small_frame(i) for i in (6, 7, 8)]
+    W, H, D = frames[0]["W"], frames[0]["H"], frames[0]["D"]
+    p = sldf.default_params(width=W, height=H, max_disp=D, batch=3, **SMALL)
+    ctx = sldf.Context(p)
+    left = sldf.device_images(np.stack([f["left"] for f in frames]))
+    right = sldf.device_images(np.stack([f["right"] for f in frames]))
+    lid = torch.stack([sldf.quantize_lidar(torch.from_numpy(f["lidar"]).cuda(), D)
+                       for f in frames])
+    disp, valid = ctx.run_batch(left, right, lid)
+    torch.cuda.synchronize()
+    for i, f in enumerate(frames):
+        pkw = _params(W, H, D, **SMALL)
+        o = run_oracle(f, pkw)
+        assert (valid[i].cpu().numpy() == o["valid"]).all()
+        assert np.abs(disp[i].cpu().numpy() - o["disp"]).max() <= SUB_TOL
+
+
+def test_paper_scale_batch_launch_configuration():
+    """The benchmark's launch configuration (8 frames per batch call) at
+    1242 x 375, D = 128: first and last frame against the oracle, the others
+    against single-frame runs."""
+    B = 8
+    frames = [synth.kitti_frame(i) for i in range(B)]
+    p = sldf.default_params(batch=B)
+    ctx = sldf.Context(p)
+    left = sldf.device_images(np.stack([f["left"] for f in frames]))
+    right = sldf.device_images(np.stack([f["right"] for f in frames]))
+    lid = torch.stack([sldf.quantize_lidar(torch.from_numpy(f["lidar"]).cuda(), 128)
+                       for f in frames])
+    disp, valid = ctx.run_batch(left, right, lid)
+    torch.cuda.synchronize()
+    disp, valid = disp.cpu().numpy(), valid.cpu().numpy()
+    pkw = _params(1242, 375, 128)
+    for i in (0, B - 1):
+        print(f"case kitti batch frame {i}", flush=True)
+        o = run_oracle(frames[i], pkw)
+        assert (valid[i] == o["valid"]).all()
+        assert np.abs(disp[i] - o["disp"]).max() <= SUB_TOL
+    for i in range(1, B - 1):
+        g = run_gpu(frames[i], pkw, taps=False)
+        assert (g["valid"] == valid[i]).all() and (g["disp"] == disp[i]).all()
+
+
+def test_deterministic_repeat():
+    f = synth.small_frame(9)
+    pkw = _params(f["W"], f["H"], f["D"], **SMALL)
+    a, b = run_gpu(f, pkw), run_gpu(f, pkw)
+    for k in ("disp", "valid", "S", "dstar", "dright", "dsub"):
+        assert (a[k] == b[k]).all()
+
+
+def test_run_rejects_misaligned_pitch():
+    p = sldf.default_params(width=64, height=32, max_disp=64, **SMALL)
+    ctx = sldf.Context(p)
+    img = torch.zeros((32, 72), dtype=torch.uint8, device="cuda")[:, :64]   # pitch 72
+    lid = torch.full((32, 64), -1, dtype=torch.int16, device="cuda")
+    with pytest.raises(sldf.SldfError) as ei:
+        ctx.run(img, img, lid)
+    assert ei.value.status == sldf.EALIGN
