@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=200)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (reference "
+                         "for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1 "
@@ -98,6 +101,17 @@ def main():
         # ingest (float LiDAR -> D-bar) + the whole method for B frames
         sldf.quantize_lidar(lid_f.view(B * H, W), D, out=lid_q.view(B * H, W))
         ctx.run_batch(left, right, lid_q, disp, valid)
+
+    if args.copy_calibration > 0:
+        # plain copy of known size: the reference reading for FETCH_SIZE /
+        # WRITE_SIZE counters (read N bytes, write N bytes)
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -138,7 +152,7 @@ def main():
     lq1 = torch.empty((H, W), dtype=torch.int16, device="cuda")
     lats = []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for i in range(args.latency_runs + 5):
+    for i in range(args.latency_runs + 5 if args.latency_runs > 0 else 0):
         j = i % B
         ev0.record(stream)
         sldf.quantize_lidar(lid_f[j], D, out=lq1)
@@ -147,7 +161,7 @@ def main():
         ev1.synchronize()
         if i >= 5:
             lats.append(ev0.elapsed_time(ev1))
-    lats = np.array(lats)
+    lats = np.array(lats) if lats else np.zeros(1)
     print(f"[bench] latency p50 {np.percentile(lats, 50):.3f} ms", file=sys.stderr, flush=True)
 
     out = dict(metric=METRIC, value=round(fps, 2), unit="frames/s", n_gpus=1, steps=K,

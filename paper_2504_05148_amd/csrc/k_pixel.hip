@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
         *reinterpret_cast<uint4*>(&tile[r][cc * 16]) = v;
     }
     __syncthreads();
-    uint32_t* out = (view ? a.out_r : a.out_l) + (int64_t)frame * a.px_stride;
+    uint32_t* out = (view ? a.out_r : a.out_l) + (int64_t)frame * a.out_fstride;
     const int lx = threadIdx.x & 63;
     for (int ty = threadIdx.x >> 6; ty < kCensusTH; ty += 4) {
         const int x = x0 + lx, y = y0 + ty;
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
                 }
             }
         }
-        out[(int64_t)y * a.W + x] = code;
+        out[(int64_t)y * a.out_pitch + x] = code;
     }
 }
 
@@ -134,9 +134,9 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int x = x0 + tx, y = y0 + ty;
     if (x >= a.W || y >= a.H) return;
-    const uint32_t* cl = a.census_l + (int64_t)frame * a.px_stride;
-    const uint32_t* cr_row = a.census_r + (int64_t)frame * a.px_stride + (int64_t)y * a.W;
-    const uint32_t c = cl[(int64_t)y * a.W + x];
+    const uint32_t* cl = a.census_l + (int64_t)frame * a.census_fstride;
+    const uint32_t* cr_row = a.census_r + (int64_t)frame * a.census_fstride + (int64_t)y * a.census_pitch;
+    const uint32_t c = cl[(int64_t)y * a.census_pitch + x];
     uint32_t best = 0xffffffffu;   // (H << 16) | d, lexicographic minimum
     for (int r = 0; r <= 2 * rs; ++r) {
         for (int q = 0; q <= 2 * rs; ++q) {

@@ -31,6 +31,7 @@ namespace sldf {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ u16x2 v2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t u1(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
@@ -52,6 +53,8 @@ constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 constexpr int kWaveShr1 = 0x138;       // lane i <- lane i-1
 constexpr int kWaveShl1 = 0x130;       // lane i <- lane i+1
+
+constexpr int kXcds = 8;               // MI355X: 8 XCDs, one L2 each
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
@@ -100,57 +103,40 @@ __device__ __forceinline__ void line_start(int line, int W, int H, int dx, int d
     }
 }
 
-// Inputs of one step (one pixel of the line) for one lane.
+// Inputs of one step (one pixel of the line) for one lane, loaded a few
+// steps ahead of their use.
 struct StepIn {
     uint32_t cb;        // census of the base pixel
-    uint32_t cm[8];     // census of the matching pixels for the lane's 8 d
+    u32x4a4 m0, m1;     // census of 8 consecutive matching pixels
     int32_t e;          // prior disparity (-1 = none)
-    uint4 s;            // partial S of the lane's 8 d (middle / last passes)
+    u32x4 s;            // partial S of the lane's 8 d (middle / last passes)
+};
+
+// Offsets of the current pixel, advanced by a constant per step.
+struct Cursor {
+    int x, y;
+    uint32_t oc;    // census offset  y * census_pitch + x + D (padded row)
+    uint32_t op;    // prior offset   y * prior_pitch + x
+    uint32_t opx;   // pixel offset   y * W + x
 };
 
 template <int D, int VIEW, bool LOAD_S>
-__device__ __forceinline__ void load_step(const SgmArgs& a, const uint32_t* cbase,
-                                          const uint32_t* cmatch, const int16_t* prior,
-                                          const uint16_t* S, int x, int y, int d0,
-                                          uint32_t maskn, StepIn& st)
+__device__ __forceinline__ void load_step(const uint32_t* __restrict__ cbase,
+                                          const uint32_t* __restrict__ cmatch,
+                                          const int16_t* __restrict__ prior,
+                                          const uint16_t* __restrict__ S, const Cursor& c,
+                                          int d0, StepIn& st)
 {
-    const int64_t row = (int64_t)y * a.W;
-    st.cb = cbase[row + x];
-    const uint32_t* mrow = cmatch + row;
-    if (VIEW == 0) {
-        // matching pixels x - d for d = d0 .. d0+7 (descending addresses)
-        const int base = x - d0 - 7;
-        if (base >= 0) {
-            u32x4a4 lo = *reinterpret_cast<const u32x4a4*>(mrow + base);
-            u32x4a4 hi = *reinterpret_cast<const u32x4a4*>(mrow + base + 4);
-            st.cm[0] = hi.w; st.cm[1] = hi.z; st.cm[2] = hi.y; st.cm[3] = hi.x;
-            st.cm[4] = lo.w; st.cm[5] = lo.z; st.cm[6] = lo.y; st.cm[7] = lo.x;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int xm = x - d0 - j;
-                st.cm[j] = xm >= 0 ? mrow[xm] : (st.cb ^ maskn);
-            }
-        }
-        st.e = prior ? (int32_t)prior[(int64_t)y * a.prior_pitch + x] : -1;
-    } else {
-        // matching pixels x + d (ascending addresses)
-        const int base = x + d0;
-        if (base + 7 < a.W) {
-            u32x4a4 lo = *reinterpret_cast<const u32x4a4*>(mrow + base);
-            u32x4a4 hi = *reinterpret_cast<const u32x4a4*>(mrow + base + 4);
-            st.cm[0] = lo.x; st.cm[1] = lo.y; st.cm[2] = lo.z; st.cm[3] = lo.w;
-            st.cm[4] = hi.x; st.cm[5] = hi.y; st.cm[6] = hi.z; st.cm[7] = hi.w;
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int xm = base + j;
-                st.cm[j] = xm < a.W ? mrow[xm] : (st.cb ^ maskn);
-            }
-        }
-        st.e = -1;
-    }
-    if (LOAD_S) st.s = *reinterpret_cast<const uint4*>(S + (row + x) * D + d0);
+    st.cb = cbase[c.oc];
+    // matching pixels: x - d (left base, descending) or x + d (right base)
+    // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
+    const uint32_t om = VIEW == 0 ? c.oc - (uint32_t)(d0 + 7) : c.oc + (uint32_t)d0;
+    st.m0 = *reinterpret_cast<const u32x4a4*>(cmatch + om);
+    st.m1 = *reinterpret_cast<const u32x4a4*>(cmatch + om + 4);
+    if (VIEW == 0) st.e = prior ? (int32_t)prior[c.op] : -1;
+    // S streams through once per pass: non-temporal, so it does not evict
+    // the census rows that neighbouring lines re-read from L2
+    if (LOAD_S) st.s = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(S + (size_t)c.opx * D + d0));
 }
 
 template <int G, int MODE, int VIEW>
@@ -159,41 +145,79 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
 {
     constexpr int D = G * 8;
     constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
-    constexpr bool kWta = MODE == kLast || MODE == kSingle;
-    int x, y, len;
-    line_start(line, a.W, a.H, a.dx, a.dy, x, y, len);
+    int x0, y0, len;
+    line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
-    const uint32_t* cbase = a.cbase[VIEW] + (int64_t)frame * a.px_stride;
-    const uint32_t* cmatch = a.cmatch[VIEW] + (int64_t)frame * a.px_stride;
-    const int16_t* prior = VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
-    uint16_t* S = a.S[VIEW] + (int64_t)frame * a.S_stride;
-    const uint32_t maskn = a.n >= 32 ? 0xffffffffu : ((1u << a.n) - 1u);
+    // census rows are addressed from their padded start (pixel x at x + D),
+    // so every offset below is non-negative
+    const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
+    const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
+    const int16_t* __restrict__ prior =
+        VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
+    uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
     const uint32_t p1x2 = a.p1s * 0x10001u;
+    const uint32_t nfill = (uint32_t)a.n;
     const bool gfirst = g == 0, glast = g == G - 1;
+    const int W = a.W;
+    // per-step offset increments
+    const uint32_t dc = (uint32_t)(a.dy * a.census_pitch + a.dx);
+    const uint32_t dp = (uint32_t)(a.dy * a.prior_pitch + a.dx);
+    const uint32_t dpx = (uint32_t)(a.dy * W + a.dx);
+
+    Cursor cl;   // cursor of the next load
+    cl.x = x0;
+    cl.y = y0;
+    cl.oc = (uint32_t)(y0 * a.census_pitch + x0 + D);
+    cl.op = (uint32_t)(y0 * a.prior_pitch + x0);
+    cl.opx = (uint32_t)(y0 * W + x0);
+    Cursor cc = cl;   // cursor of the step being computed
+    auto advance = [&](Cursor& c) {
+        c.x += a.dx;
+        c.y += a.dy;
+        c.oc += dc;
+        c.op += dp;
+        c.opx += dpx;
+    };
 
     uint32_t L[4] = {0, 0, 0, 0};
     uint32_t m = 0;
-    StepIn cur, nxt;
-    load_step<D, VIEW, kLoadS>(a, cbase, cmatch, prior, S, x, y, d0, maskn, cur);
-    for (int t = 0; t < len; ++t) {
-        const int xn = x + a.dx, yn = y + a.dy;
-        if (t + 1 < len) load_step<D, VIEW, kLoadS>(a, cbase, cmatch, prior, S, xn, yn, d0, maskn, nxt);
 
-        // ---- joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4, scaled) ----
+    auto step = [&](const StepIn& in, int t) {
+        // ---- joint cost C'(p, d), d = d0 .. d0+7 (Eq. 4, scaled) ----
+        uint32_t mc[8];
+        if (VIEW == 0) {
+            mc[0] = in.m1.w; mc[1] = in.m1.z; mc[2] = in.m1.y; mc[3] = in.m1.x;
+            mc[4] = in.m0.w; mc[5] = in.m0.z; mc[6] = in.m0.y; mc[7] = in.m0.x;
+        } else {
+            mc[0] = in.m0.x; mc[1] = in.m0.y; mc[2] = in.m0.z; mc[3] = in.m0.w;
+            mc[4] = in.m1.x; mc[5] = in.m1.y; mc[6] = in.m1.z; mc[7] = in.m1.w;
+        }
         uint32_t h[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(cur.cb ^ cur.cm[j]);
-        uint32_t C[4];
-        // values outside [0, D) carry no prior (the ABI only admits -1 there)
-        const bool has = (unsigned)cur.e < (unsigned)D;
-        const uint32_t mulh = (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u;
-        if (VIEW == 0 && has) {
-            // DDC pattern entry for disparity d sits at index d - e + D
-            const int s = d0 - cur.e + D;
-            const uint32_t* pp = (s & 1) ? pat + (D + 8) + ((s - 1) >> 1) : pat + (s >> 1);
+        for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
+        // matching pixel outside the image: all n bits differ
+        if (VIEW == 0 ? cc.x < d0 + 7 : cc.x + d0 + 7 >= W) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pp[i]);
+            for (int j = 0; j < 8; ++j) {
+                const bool out = VIEW == 0 ? cc.x - d0 - j < 0 : cc.x + d0 + j >= W;
+                h[j] = out ? nfill : h[j];
+            }
+        }
+        uint32_t C[4];
+        if (VIEW == 0) {
+            // values outside [0, D) carry no prior (the ABI only admits -1)
+            const bool has = (unsigned)in.e < (unsigned)D;
+            const uint32_t mulh = (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u;
+            // DDC of disparity d sits at pattern entry d - e + D; no prior
+            // reads the zero run at the end of the table
+            const int sidx = d0 - in.e + D;
+            const int base = has ? ((sidx & 1) ? (D + 8) + ((sidx - 1) >> 1) : (sidx >> 1))
+                                 : 2 * (D + 8);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pat[base + i]);
         } else {
+            const uint32_t mulh = a.mulh_noprior * 0x10001u;
 #pragma unroll
             for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, 0u);
         }
@@ -230,24 +254,25 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
         }
 
         // ---- aggregated sum S (Eq. 3) ----
-        const int64_t cell = ((int64_t)y * a.W + x) * D + d0;
+        uint16_t* sp = S + (size_t)cc.opx * D + d0;
         if (MODE == kFirst) {
-            *reinterpret_cast<uint4*>(S + cell) = make_uint4(L[0], L[1], L[2], L[3]);
+            __builtin_nontemporal_store(u32x4{L[0], L[1], L[2], L[3]},
+                                        reinterpret_cast<u32x4*>(sp));
         } else if (MODE == kMiddle) {
-            uint4 o = make_uint4(pk_add(cur.s.x, L[0]), pk_add(cur.s.y, L[1]),
-                                 pk_add(cur.s.z, L[2]), pk_add(cur.s.w, L[3]));
-            *reinterpret_cast<uint4*>(S + cell) = o;
+            __builtin_nontemporal_store(
+                u32x4{pk_add(in.s.x, L[0]), pk_add(in.s.y, L[1]), pk_add(in.s.z, L[2]),
+                      pk_add(in.s.w, L[3])},
+                reinterpret_cast<u32x4*>(sp));
         } else {
             uint32_t St[4];
             if (MODE == kLast) {
-                St[0] = pk_add(cur.s.x, L[0]); St[1] = pk_add(cur.s.y, L[1]);
-                St[2] = pk_add(cur.s.z, L[2]); St[3] = pk_add(cur.s.w, L[3]);
+                St[0] = pk_add(in.s.x, L[0]); St[1] = pk_add(in.s.y, L[1]);
+                St[2] = pk_add(in.s.z, L[2]); St[3] = pk_add(in.s.w, L[3]);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) St[i] = L[i];
             }
-            if (a.store_sum)
-                *reinterpret_cast<uint4*>(S + cell) = make_uint4(St[0], St[1], St[2], St[3]);
+            if (a.store_sum) *reinterpret_cast<uint4*>(sp) = make_uint4(St[0], St[1], St[2], St[3]);
             // ---- WTA, Eq. 3: lexicographic minimum of (S, d) ----
             uint32_t best = 0xffffffffu;
 #pragma unroll
@@ -258,10 +283,10 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
             }
             best = group_min<G>(best);
             const int db = (int)(best & 511u);
-            uint32_t spv = dpp<kWaveShr1>(St[3]);
-            uint32_t snx = dpp<kWaveShl1>(St[0]);
+            const uint32_t spv = dpp<kWaveShr1>(St[3]);
+            const uint32_t snx = dpp<kWaveShl1>(St[0]);
             if (db >= d0 && db < d0 + 8) {
-                const int64_t px = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
+                const size_t px = (size_t)frame * a.px_stride + cc.opx;
                 a.wta[VIEW][px] = (int16_t)db;
                 if (VIEW == 0) {
                     // cells d0-1 .. d0+8 of S
@@ -286,15 +311,37 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
                     float v = (float)db;
                     if (a.subpixel && db > 0 && db < D - 1) {
                         int den = (int)A - 2 * (int)B + (int)Cc;
-                        if (den > 0) v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
+                        if (den > 0)
+                            v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
                     }
                     a.dsub[px] = v;
                 }
             }
         }
-        x = xn;
-        y = yn;
-        cur = nxt;
+        advance(cc);
+    };
+
+    // three steps in flight: the loads of step t+3 are issued once step t
+    // has consumed its buffer
+    StepIn b0, b1, b2;
+    load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b0);
+    advance(cl);
+    if (len > 1) load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b1);
+    advance(cl);
+    if (len > 2) load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b2);
+    advance(cl);
+    for (int t = 0; t < len; t += 3) {
+        step(b0, t);
+        if (t + 3 < len) load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b0);
+        advance(cl);
+        if (t + 1 >= len) break;
+        step(b1, t + 1);
+        if (t + 4 < len) load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b1);
+        advance(cl);
+        if (t + 2 >= len) break;
+        step(b2, t + 2);
+        if (t + 5 < len) load_step<D, VIEW, kLoadS>(cbase, cmatch, prior, S, cl, d0, b2);
+        advance(cl);
     }
 }
 
@@ -302,30 +349,43 @@ template <int G, int MODE>
 __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
 {
     constexpr int D = G * 8;
-    // DDC pattern (Eq. 4 term divided out of the cost: 0 at the prior, Q1 at
-    // +-1, Q2 beyond), as pairs of u16 starting at even (first half) and odd
-    // (second half) entries of P[k] = ddc(k - D), k in [0, 2D + 16).
-    __shared__ uint32_t pat[2 * (D + 8)];
-    for (int i = threadIdx.x; i < 2 * (D + 8); i += 256) {
-        const int half = i >= D + 8;
-        const int k0 = 2 * (i - half * (D + 8)) + half;
-        uint32_t v[2];
+    // DDC pattern (the Eq. 4 term: 0 at the prior, Q1 at +-1, Q2 beyond), as
+    // pairs of u16 starting at even (first half) and odd (second half)
+    // entries of P[k] = ddc(k - D), k in [0, 2D + 16), followed by a run of
+    // zeros used where a pixel has no prior.
+    __shared__ uint32_t pat[2 * (D + 8) + 4];
+    for (int i = threadIdx.x; i < 2 * (D + 8) + 4; i += 256) {
+        uint32_t v[2] = {0u, 0u};
+        if (i < 2 * (D + 8)) {
+            const int half = i >= D + 8;
+            const int k0 = 2 * (i - half * (D + 8)) + half;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            int diff = k0 + j - D;
-            diff = diff < 0 ? -diff : diff;
-            v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+            for (int j = 0; j < 2; ++j) {
+                int diff = k0 + j - D;
+                diff = diff < 0 ? -diff : diff;
+                v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+            }
         }
         pat[i] = v[0] | (v[1] << 16);
     }
     __syncthreads();
+    // XCD-aware mapping: blocks are dispatched round-robin over the 8 XCDs
+    // (physical block b runs on XCD b % 8).  Give each XCD a contiguous range
+    // of logical blocks, so the lines of one frame-view share one L2 and its
+    // copy of that view's census rows.
+    const int nb = gridDim.x;                 // a multiple of kXcds
+    const int b = blockIdx.x;
+    const int logical = (b % kXcds) * (nb / kXcds) + b / kXcds;
+    const int fv = logical / a.blocks_per_fv;
+    if (fv >= a.n_fv) return;
+    const int view = fv % a.nviews, frame = fv / a.nviews;
     const int g = threadIdx.x % G;
-    const int line = blockIdx.x * (256 / G) + threadIdx.x / G;
+    const int line = (logical - fv * a.blocks_per_fv) * (256 / G) + threadIdx.x / G;
     if (line >= a.nlines) return;
-    if (blockIdx.y == 0)
-        run_line<G, MODE, 0>(a, pat, line, g, blockIdx.z);
+    if (view == 0)
+        run_line<G, MODE, 0>(a, pat, line, g, frame);
     else
-        run_line<G, MODE, 1>(a, pat, line, g, blockIdx.z);
+        run_line<G, MODE, 1>(a, pat, line, g, frame);
 }
 
 template <int G>
@@ -339,12 +399,17 @@ static void launch_g(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
     }
 }
 
-hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+hipError_t launch_sgm_dir(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
                           hipStream_t s)
 {
     const int G = D / 8;
     const int lines_per_block = 256 / G;
-    dim3 grid((a.nlines + lines_per_block - 1) / lines_per_block, nviews, nframes);
+    SgmArgs a = a0;
+    a.blocks_per_fv = (a.nlines + lines_per_block - 1) / lines_per_block;
+    a.nviews = nviews;
+    a.n_fv = nviews * nframes;
+    const int64_t nb = (int64_t)a.blocks_per_fv * a.n_fv;
+    dim3 grid((unsigned)((nb + kXcds - 1) / kXcds * kXcds));
     if (G == 8) launch_g<8>(a, mode, grid, s);
     else if (G == 16) launch_g<16>(a, mode, grid, s);
     else launch_g<32>(a, mode, grid, s);

@@ -89,8 +89,10 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         off = align_up(off + bytes, 256);
         return base ? (void*)(base + o) : nullptr;
     };
-    void* cl = seg(F * px * 4);
-    void* cr = seg(F * px * 4);
+    const size_t cpitch = (size_t)p->width + 2 * (size_t)p->max_disp;
+    const size_t cframe = cpitch * (size_t)p->height;
+    void* cl = seg(F * cframe * 4);
+    void* cr = seg(F * cframe * 4);
     void* pr = p->semidense ? seg(F * px * 2) : nullptr;
     void* ds = seg(F * px * 2);
     void* dr = seg(F * px * 2);
@@ -98,8 +100,10 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* sl = seg(F * cells * 2);
     void* sr = needs_right(p) ? seg(F * cells * 2) : nullptr;
     if (b) {
-        b->census_l = (uint32_t*)cl;
-        b->census_r = (uint32_t*)cr;
+        b->census_l = base ? (uint32_t*)cl + p->max_disp : nullptr;
+        b->census_r = base ? (uint32_t*)cr + p->max_disp : nullptr;
+        b->census_pitch = (int32_t)cpitch;
+        b->census_fstride = (int64_t)cframe;
         b->prior = (int16_t*)pr;
         b->dstar = (int16_t*)ds;
         b->dright = (int16_t*)dr;
@@ -318,7 +322,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ca.img_fstride = img_frame_stride;
     ca.out_l = b.census_l;
     ca.out_r = b.census_r;
-    ca.px_stride = b.px_stride;
+    ca.out_pitch = b.census_pitch;
+    ca.out_fstride = b.census_fstride;
     ca.W = W;
     ca.H = H;
     ca.cw = p.census_w;
@@ -335,6 +340,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         SemiArgs sa;
         sa.census_l = b.census_l;
         sa.census_r = b.census_r;
+        sa.census_pitch = b.census_pitch;
+        sa.census_fstride = b.census_fstride;
         sa.lidar = lidar;
         sa.lidar_pitch = lidar_pitch;
         sa.lidar_fstride = lidar_frame_stride;
@@ -360,6 +367,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.cmatch[0] = b.census_r;
     ga.cbase[1] = b.census_r;
     ga.cmatch[1] = b.census_l;
+    ga.census_pitch = b.census_pitch;
+    ga.census_fstride = b.census_fstride;
     ga.prior = prior;
     ga.prior_pitch = prior_pitch;
     ga.prior_fstride = prior_fstride;
@@ -424,8 +433,13 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     auto cp = [&](void* dst, const void* src, size_t bytes) {
         return dst && src ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s) : hipSuccess;
     };
-    if (cp(t.census_l, b.census_l, px * 4) != hipSuccess ||
-        cp(t.census_r, b.census_r, px * 4) != hipSuccess ||
+    auto cp_census = [&](void* dst, const uint32_t* src) {
+        return dst ? hipMemcpy2DAsync(dst, (size_t)W * 4, src, (size_t)b.census_pitch * 4,
+                                      (size_t)W * 4, H, hipMemcpyDeviceToDevice, s)
+                   : hipSuccess;
+    };
+    if (cp_census(t.census_l, b.census_l) != hipSuccess ||
+        cp_census(t.census_r, b.census_r) != hipSuccess ||
         cp(t.dstar, b.dstar, px * 2) != hipSuccess ||
         cp(t.dsub, b.dsub, px * 4) != hipSuccess ||
         cp(t.cost_sum, b.S_left, px * D * 2) != hipSuccess)

@@ -8,9 +8,15 @@ namespace sldf {
 
 // Workspace segments of one context (segment-major: every segment holds all
 // batch frames back to back with the stated frame stride, in elements).
+// Census rows are padded by D codes on both sides so that every matching
+// pixel x -+ d of a disparity range lies inside the allocation; census_l and
+// census_r point at pixel (0, 0) of frame 0 (pad included before it) and
+// pixel (x, y) of frame f sits at f * census_fstride + y * census_pitch + x.
 struct Buffers {
-    uint32_t* census_l;   // [F][H][W]
-    uint32_t* census_r;   // [F][H][W]
+    uint32_t* census_l;
+    uint32_t* census_r;
+    int32_t census_pitch;     // W + 2 D
+    int64_t census_fstride;   // H * census_pitch
     int16_t* prior;       // [F][H][W]  semidense map (SDSGM only)
     int16_t* dstar;       // [F][H][W]
     int16_t* dright;      // [F][H][W]
@@ -28,13 +34,16 @@ struct CensusArgs {
     int64_t img_fstride;
     uint32_t* out_l;
     uint32_t* out_r;
-    int64_t px_stride;
+    int32_t out_pitch;
+    int64_t out_fstride;
     int32_t W, H, cw, ch;
 };
 
 struct SemiArgs {
     const uint32_t* census_l;
     const uint32_t* census_r;
+    int32_t census_pitch;
+    int64_t census_fstride;
     const int16_t* lidar;
     int32_t lidar_pitch;
     int64_t lidar_fstride;
@@ -46,6 +55,8 @@ struct SemiArgs {
 struct SgmArgs {
     const uint32_t* cbase[2];   // base-view census per view (left, right)
     const uint32_t* cmatch[2];  // matching-view census per view
+    int32_t census_pitch;
+    int64_t census_fstride;
     const int16_t* prior;       // left-view prior (D-hat / D-bar)
     int32_t prior_pitch;
     int64_t prior_fstride;
@@ -64,6 +75,10 @@ struct SgmArgs {
     uint32_t p1s, p2s;          // den * P1, den * P2
     int32_t subpixel;
     int32_t store_sum;          // last pass also stores S (debug tap)
+    // launch geometry (filled by launch_sgm_dir)
+    int32_t blocks_per_fv;      // blocks per (frame, view)
+    int32_t nviews;
+    int32_t n_fv;               // frames * views
 };
 
 struct CheckArgs {
