@@ -88,9 +88,20 @@ typedef struct {
                               (Tab. II: 2, 20); 0 <= rc <= 31 */
     int32_t check_mode;    /* 0 none, 1 stereo only, 2 LiDAR only,
                               3 stereo OR LiDAR (Eq. 6; Tab. V variants) */
-    int32_t check_impl;    /* 0: plain right-view pass (only value accepted) */
+    int32_t check_impl;    /* 0: plain check with the right-view SGM pass;
+                              1: learned check (needs check_mode 3 and weights,
+                              see sldf_surrogate_set_weights): a small CNN on
+                              left-view cost features replaces the stereo
+                              half of Eq. 6, the right-view pass is skipped
+                              unless the fallback triggers */
     int32_t subpixel;      /* 1: parabola fit (Sec. III end), 0: integer */
     int32_t batch;         /* max frames per sldf_run_batch call (>= 1) */
+    float fallback_tau;    /* learned check: when more than tau * W * H pixels
+                              of a frame are undecided by LiDAR and have
+                              |logit| < uncertain_margin, that frame falls
+                              back to the plain check (decided on the device,
+                              no host synchronisation); in [0, 1] */
+    float uncertain_margin;  /* >= 0 */
 } sldf_params;
 
 /* Optional debug taps: device pointers, any may be NULL.  Written for frame
@@ -100,7 +111,17 @@ typedef struct {
      cost_sum            uint16 [H][W][D] aggregated left cost S (Eq. 3 sum)
      dstar               int16  [H][W]   integer left disparity d*
      dright              int16  [H][W]   right-view disparity d'
-     dsub                float  [H][W]   subpixel d* before the check */
+     dsub                float  [H][W]   subpixel d* before the check
+     rho                 uint16 [H][W]   LiDAR residual: min |d* - v| over the
+                                         valid raw sparse values v in the check
+                                         window (65535 = none); the LiDAR half
+                                         of Eq. 6 is rho <= Tc
+     features            uint16 [H][W][8] bf16 inputs of the learned check:
+                                         S(d*), second minimum of S over
+                                         |d - d*| >= 2, curvature
+                                         S(d*-1) - 2 S(d*) + S(d*+1), each times
+                                         1 / (num_paths P2'); d* / D;
+                                         min(rho, 32) / 32; three zeros */
 typedef struct {
     uint32_t* census_l;
     uint32_t* census_r;
@@ -109,6 +130,8 @@ typedef struct {
     int16_t* dstar;
     int16_t* dright;
     float* dsub;
+    uint16_t* rho;
+    uint16_t* features;
 } sldf_taps;
 
 typedef struct sldf_ctx sldf_ctx;
@@ -184,14 +207,70 @@ sldf_status sldf_lidar_quantize(const float* in, int32_t width, int32_t height,
    events for up to n runs (host-side HIP events, no device memory) and
    starts recording; n = 0 stops and frees them.  Stages:
      0 census, 1 semidensification, 2 SGM path passes (all directions, both
-     views), 3 consistency check.
+     views; left view only for the learned check), 3 check, 4 fallback.
    sldf_timing_read waits for the recorded events, writes the summed
-   milliseconds per stage into ms[4] and the number of kernel launches per
-   stage into launches[4] (host arrays), and resets the counters.
-   Errors: EINVAL, ESTATE (not enabled / more runs than events), EDEVICE. */
-#define SLDF_NUM_STAGES 4
+   milliseconds per stage into ms[5] and the number of SGM-pass / other
+   kernel launches per stage into launches[5] (host arrays), and resets
+   the counters.
+   Errors: EINVAL, ESTATE (not enabled / more runs than events), EDEVICE.
+   Stage 3 holds the LiDAR window pass and the plain check, or the CNN and
+   the learned mask; stage 4 the gated fallback (right-view SGM + plain
+   check) of the learned check (empty for the plain check). */
+#define SLDF_NUM_STAGES 5
 sldf_status sldf_timing_enable(sldf_ctx* ctx, int32_t max_runs);
 sldf_status sldf_timing_read(sldf_ctx* ctx, double* ms, int64_t* launches);
+
+/* ---- Learned consistency check (an extension beside the paper's method;
+   the plain check of Eq. 6 stays the reference and the fallback) ----
+   Network: 3x3 convolutions with dilations 1, 2, 4, 8; channels
+   5 (+3 zero) -> 32 -> 32 -> 32 -> 1; ReLU after the first three; bf16
+   weights and activations, fp32 accumulation; logit > 0 means "consistent".
+   Parameter blob (device, caller-owned, may be shared by contexts):
+     weights: bf16 (uint16 bit patterns), sldf_surrogate_num_weights() of
+              them: layer l stored as [9 taps][out][in] with taps in raster
+              order of the 3x3 grid and (out, in) = (32, 8), (32, 32),
+              (32, 32), (16, 32) (padding rows / columns zero);
+     biases:  float, 32 + 32 + 32 + 1. */
+int32_t sldf_surrogate_num_weights(void);
+int32_t sldf_surrogate_num_biases(void);
+
+/* Attach the surrogate parameters used when check_impl = 1 (pointers are
+   kept, not copied; NULL detaches).  Errors: EINVAL. */
+sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
+                                       const float* biases);
+
+/* Forward pass on given inputs (device): x0 bf16 [F][H][W][8] (the
+   `features` tap layout) -> logits float [F][H][W]; act1..act3 bf16
+   [F][H][W][32] receive the hidden activations (all three required).
+   Errors: EINVAL, EDEVICE. */
+sldf_status sldf_surrogate_forward(const uint16_t* x0, int32_t width, int32_t height,
+                                   int32_t n_frames, const uint16_t* weights,
+                                   const float* biases, uint16_t* act1, uint16_t* act2,
+                                   uint16_t* act3, float* logits, void* hip_stream);
+
+/* Device workspace bytes of sldf_surrogate_train_step for F frames. */
+sldf_status sldf_surrogate_train_workspace_size(int32_t width, int32_t height,
+                                                int32_t n_frames, size_t* bytes);
+
+/* One training step on F frames (all device pointers): forward, binary
+   cross-entropy on the pixels the LiDAR test leaves undecided (rho > tc)
+   against labels (the plain check's mask, uint8 [F][H][W]), backward
+   (dgrad + wgrad on the matrix cores, deterministic reductions) and, when
+   apply_update != 0, one Adam step (bias-corrected, step >= 1) on the fp32
+   master parameters (master, adam_m, adam_v: num_weights + num_biases
+   floats, weights first), rewriting weights (bf16) and biases in place.
+   grads_out (optional, same layout as master) receives the gradient;
+   stats_out (optional, 3 floats) the mean loss, the number of undecided
+   pixels and the number of pixels whose learned mask equals the label.
+   Errors: EINVAL, ENOMEM (workspace too small), EDEVICE. */
+sldf_status sldf_surrogate_train_step(const uint16_t* x0, const uint8_t* labels,
+                                      const uint16_t* rho, int32_t tc, int32_t width,
+                                      int32_t height, int32_t n_frames, float* master,
+                                      float* adam_m, float* adam_v, uint16_t* weights,
+                                      float* biases, float lr, float beta1, float beta2,
+                                      float eps, int32_t step, int32_t apply_update,
+                                      void* workspace, size_t ws_bytes, float* grads_out,
+                                      float* stats_out, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -186,6 +186,41 @@ def check(dstar, dright, lidar, dsub, tc, rc, mode):
     return disp, valid
 
 
+def lidar_residual(dstar, lidar, D, rc):
+    """rho = min |d* - v| over valid sparse values in the (2 rc + 1)^2 window;
+    65535 where there is none (uint16 [H, W])."""
+    ds = np.ascontiguousarray(dstar, np.int32)
+    li = np.ascontiguousarray(lidar, np.int16)
+    H, W = ds.shape
+    out = np.empty((H, W), np.uint16)
+    _chk(_load().orc_lidar_residual(_p(ds, i32), _p(li, i16), W, H, D, rc,
+                                    _p(out, ctypes.c_uint16)))
+    return out
+
+
+def surrogate_features(S, dstar, rho, num_paths, P2s):
+    """float32 [H, W, 5] surrogate inputs (see sldf_oracle.c)."""
+    s = np.ascontiguousarray(S, np.int32)
+    H, W, D = s.shape
+    ds = np.ascontiguousarray(dstar, np.int32)
+    r = np.ascontiguousarray(rho, np.uint16)
+    out = np.empty((H, W, 5), np.float32)
+    _chk(_load().orc_surrogate_features(_p(s, i32), _p(ds, i32), _p(r, ctypes.c_uint16),
+                                        W, H, D, num_paths, P2s, _p(out, f32)))
+    return out
+
+
+def bf16_round(x):
+    """float32 -> bfloat16 bit patterns (uint16), round to nearest even."""
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return u.astype(np.uint16)
+
+
+def bf16_to_f32(b):
+    return (np.ascontiguousarray(b, np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
 def run(params: OracleParams, left, right, lidar_q, taps: bool = False):
     """Whole pipeline for one frame.  lidar_q is the int16 sparse map (-1 =
     invalid).  Returns (disp, valid) or, with taps, a dict of every

@@ -346,6 +346,72 @@ int orc_check(const int32_t* dstar, const int32_t* dright, const int16_t* lidar,
 }
 
 /* ------------------------------------------------------------------------ */
+/* LiDAR residual: rho_p = min over valid raw sparse values v in the         */
+/* (2 rc + 1)^2 window K_p (clipped) of |d*_p - v|; 65535 where the window   */
+/* holds none.  The LiDAR half of Eq. 6 is exactly rho_p <= Tc.              */
+/* ------------------------------------------------------------------------ */
+int orc_lidar_residual(const int32_t* dstar, const int16_t* lidar, int W, int H,
+                       int D, int rc, uint16_t* rho)
+{
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int d = dstar[y * W + x];
+            int best = 65535;
+            for (int qy = y - rc; qy <= y + rc; ++qy) {
+                if (qy < 0 || qy >= H) continue;
+                for (int qx = x - rc; qx <= x + rc; ++qx) {
+                    if (qx < 0 || qx >= W) continue;
+                    int v = lidar[qy * W + qx];
+                    if (v < 0 || v >= D) continue;
+                    int diff = d - v;
+                    if (diff < 0) diff = -diff;
+                    if (diff < best) best = diff;
+                }
+            }
+            rho[y * W + x] = (uint16_t)best;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Input features of the learned consistency surrogate (an extension beside
+   the paper's method; the plain check of Eq. 6 stays the reference).  Per
+   pixel, from the aggregated left cost S and d*:
+     f0 = S(d*)                          * sS
+     f1 = min_{|d - d*| >= 2} S(d)       * sS
+     f2 = S(d*-1) - 2 S(d*) + S(d*+1)    * sS   (0 at d* = 0 or D-1)
+     f3 = d*                             * (1 / D)
+     f4 = min(rho, 32)                   * (1 / 32)
+   with sS = 1 / (num_paths * P2'); each product is one float32 multiply of
+   the integer by the float32 scale.  out is float [H][W][5]. */
+int orc_surrogate_features(const int32_t* S, const int32_t* dstar, const uint16_t* rho,
+                           int W, int H, int D, int num_paths, int P2s, float* out)
+{
+    const float sS = 1.0f / (float)(num_paths * P2s);
+    const float sD = 1.0f / (float)D;
+    const float sR = 1.0f / 32.0f;
+    for (int i = 0; i < W * H; ++i) {
+        const int32_t* s = S + (size_t)i * D;
+        int d = dstar[i];
+        int second = 1 << 30;
+        for (int k = 0; k < D; ++k) {
+            int diff = k - d;
+            if (diff < 0) diff = -diff;
+            if (diff >= 2 && s[k] < second) second = s[k];
+        }
+        int curv = 0;
+        if (d > 0 && d < D - 1) curv = s[d - 1] - 2 * s[d] + s[d + 1];
+        int r = rho[i] < 32 ? rho[i] : 32;
+        out[(size_t)i * 5 + 0] = (float)s[d] * sS;
+        out[(size_t)i * 5 + 1] = (float)second * sS;
+        out[(size_t)i * 5 + 2] = (float)curv * sS;
+        out[(size_t)i * 5 + 3] = (float)d * sD;
+        out[(size_t)i * 5 + 4] = (float)r * sR;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole pipeline for one frame (Fig. 1 flow): semidensification (SDSGM     */
 /* only), joint cost, path aggregation, WTA + subpixel on the left view,    */
 /* the same SGM with the right image as base and no prior, and the check.   */

@@ -165,35 +165,15 @@ hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s)
 // disparity d keeps its (subpixel) disparity if
 //   stereo: the matched right pixel (x - d, y) exists and |d - d'| <= 1, or
 //   LiDAR:  some valid raw sparse value in the (2 rc + 1)^2 window (clipped)
-//           is within Tc of d;
+//           is within Tc of d, i.e. the residual rho (window bitset pass) is
+//           <= Tc;
 // mode selects stereo only (1), LiDAR only (2), both (3) or no check (0).
-// Block: 32 x 8 pixels; the LiDAR window tile is staged in LDS.
 // ---------------------------------------------------------------------------
-constexpr int kChkTW = 32, kChkTH = 8, kChkMaxR = 31;
-constexpr int kChkLW = kChkTW + 2 * kChkMaxR, kChkLH = kChkTH + 2 * kChkMaxR;
-
 __global__ __launch_bounds__(256) void check_kernel(CheckArgs a)
 {
-    __shared__ int16_t tile[kChkLH][kChkLW];
     const int frame = blockIdx.z;
-    const int rc = a.rc;
-    const int x0 = blockIdx.x * kChkTW, y0 = blockIdx.y * kChkTH;
-    const bool use_lidar = (a.mode & 2) != 0;
-    if (use_lidar) {
-        const int16_t* lid = a.lidar + (int64_t)frame * a.lidar_fstride;
-        const int lw = kChkTW + 2 * rc, lh = kChkTH + 2 * rc;
-        for (int i = threadIdx.x; i < lw * lh; i += 256) {
-            int r = i / lw, c = i - r * lw;
-            int gy = y0 - rc + r, gx = x0 - rc + c;
-            int16_t v = -1;
-            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                v = lid[(int64_t)gy * a.lidar_pitch + gx];
-            tile[r][c] = v;
-        }
-        __syncthreads();
-    }
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int x = x0 + tx, y = y0 + ty;
+    if (a.gate && a.gate[frame] <= a.gate_limit) return;   // fallback not needed
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= a.W || y >= a.H) return;
     const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
     const int d = a.dstar[p];
@@ -201,23 +181,11 @@ __global__ __launch_bounds__(256) void check_kernel(CheckArgs a)
     if (a.mode & 1) {
         int xm = x - d;
         if (xm >= 0) {
-            int dr = a.dright[p - x + xm];
-            int diff = d - dr;
+            int diff = d - a.dright[p - x + xm];
             valid = diff >= -1 && diff <= 1;
         }
     }
-    if (use_lidar && !valid) {
-        for (int r = 0; r <= 2 * rc && !valid; ++r) {
-            for (int q = 0; q <= 2 * rc; ++q) {
-                int v = tile[ty + r][tx + q];
-                int diff = d - v;
-                if (v >= 0 && diff >= -a.tc && diff <= a.tc) {
-                    valid = true;
-                    break;
-                }
-            }
-        }
-    }
+    if ((a.mode & 2) && !valid) valid = (int)a.rho[p] <= a.tc;
     const int64_t o = (int64_t)frame * a.out_fstride + (int64_t)y * a.out_pitch + x;
     a.valid_out[o] = valid ? 1 : 0;
     a.disp_out[o] = valid ? a.dsub[p] : -1.0f;
@@ -225,7 +193,7 @@ __global__ __launch_bounds__(256) void check_kernel(CheckArgs a)
 
 hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s)
 {
-    dim3 grid((a.W + kChkTW - 1) / kChkTW, (a.H + kChkTH - 1) / kChkTH, nframes);
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, nframes);
     hipLaunchKernelGGL(check_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -285,6 +285,18 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
             const int db = (int)(best & 511u);
             const uint32_t spv = dpp<kWaveShr1>(St[3]);
             const uint32_t snx = dpp<kWaveShl1>(St[0]);
+            // surrogate cost feature: second minimum of S over |d - d*| >= 2
+            uint32_t second = 0xffffu;
+            if (VIEW == 0 && a.feat) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int d_lo = d0 + 2 * i, d_hi = d_lo + 1;
+                    const uint32_t s_lo = St[i] & 0xffffu, s_hi = St[i] >> 16;
+                    second = (d_lo - db >= 2 || db - d_lo >= 2) ? min(second, s_lo) : second;
+                    second = (d_hi - db >= 2 || db - d_hi >= 2) ? min(second, s_hi) : second;
+                }
+                second = group_min<G>(second);
+            }
             if (db >= d0 && db < d0 + 8) {
                 const size_t px = (size_t)frame * a.px_stride + cc.opx;
                 a.wta[VIEW][px] = (int16_t)db;
@@ -309,12 +321,14 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
                         }
                     }
                     float v = (float)db;
-                    if (a.subpixel && db > 0 && db < D - 1) {
-                        int den = (int)A - 2 * (int)B + (int)Cc;
-                        if (den > 0)
-                            v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
-                    }
+                    const int den = (int)A - 2 * (int)B + (int)Cc;
+                    if (a.subpixel && db > 0 && db < D - 1 && den > 0)
+                        v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
                     a.dsub[px] = v;
+                    if (a.feat) {
+                        a.feat[2 * px] = B | (second << 16);
+                        a.feat[2 * px + 1] = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+                    }
                 }
             }
         }
@@ -378,7 +392,8 @@ __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
     const int logical = (b % kXcds) * (nb / kXcds) + b / kXcds;
     const int fv = logical / a.blocks_per_fv;
     if (fv >= a.n_fv) return;
-    const int view = fv % a.nviews, frame = fv / a.nviews;
+    const int view = a.view_base + fv % a.nviews, frame = fv / a.nviews;
+    if (a.gate && a.gate[frame] <= a.gate_limit) return;   // fallback not needed
     const int g = threadIdx.x % G;
     const int line = (logical - fv * a.blocks_per_fv) * (256 / G) + threadIdx.x / G;
     if (line >= a.nlines) return;

@@ -1,0 +1,436 @@
+// Learned consistency surrogate: a 4-layer 3x3 CNN (5 -> 32 -> 32 -> 32 -> 1
+// channels, dilations 1, 2, 4, 8, ReLU between layers) that predicts the
+// validity mask of the stereo-LiDAR check (Eq. 6) from left-view cost
+// features, so that the right-view SGM pass can be skipped.  BF16 weights and
+// activations, FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), FP32 master weights for training.
+//
+// Convolution = implicit GEMM per 16-pixel row tile:
+//   D[oc][px] += W[oc][k] * X[k][px],  k = (tap, input channel)
+// A operand (16 output channels x 32 k) comes from the LDS copy of the
+// weights, B operand (32 k x 16 pixels) is one 16-byte load of 8 input
+// channels of one neighbour pixel (NHWC).  With 32 input channels one k-step
+// is one tap; with 8 input channels one k-step covers four taps.
+// Backward: dgrad is the same convolution with tap-flipped, channel-
+// transposed weights and the ReLU gate of the layer input; wgrad is an MFMA
+// GEMM over pixels with transposed tiles staged in LDS, reduced across
+// blocks in a fixed order (deterministic).
+#include "sldf_internal.h"
+
+namespace sldf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f32(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out.
+// Block: 4 waves, 64 x 4 pixels; wave w takes row y0 + w, four 16-px tiles.
+// ---------------------------------------------------------------------------
+template <int CIN, int NMT>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+{
+    constexpr int OC = NMT * 16;                 // padded output channels
+    constexpr int KSTEPS = CIN == 32 ? 9 : 3;
+    __shared__ __align__(16) uint16_t wl[9 * OC * CIN];
+    for (int i = threadIdx.x; i < 9 * OC * CIN / 8; i += 256)
+        reinterpret_cast<uint4*>(wl)[i] = reinterpret_cast<const uint4*>(a.w)[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int frame = blockIdx.z, y = blockIdx.y * 4 + wave;
+    if (y >= a.H) return;
+    const uint16_t* x = a.x + (int64_t)frame * a.px_stride * CIN;
+    for (int xt = 0; xt < 4; ++xt) {
+        const int px = blockIdx.x * 64 + xt * 16 + j;
+        f32x4 acc[NMT];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int tap = CIN == 32 ? ks : 4 * ks + g;
+            const int ch0 = CIN == 32 ? 8 * g : 0;
+            uint4 bv = make_uint4(0, 0, 0, 0);
+            if (tap < 9) {
+                const int sx = px + (tap % 3 - 1) * a.dil, sy = y + (tap / 3 - 1) * a.dil;
+                if (px < a.W && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+                    bv = *reinterpret_cast<const uint4*>(x + ((int64_t)sy * a.W + sx) * CIN + ch0);
+            }
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) {
+                uint4 av = make_uint4(0, 0, 0, 0);
+                if (tap < 9)
+                    av = *reinterpret_cast<const uint4*>(wl + (tap * OC + 16 * mt + j) * CIN + ch0);
+                acc[mt] = mfma16(av, bv, acc[mt]);
+            }
+        }
+        if (px >= a.W) continue;
+        const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
+        // lane holds pixel j, output channels 16 mt + 4 g + e
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) {
+            const int oc0 = 16 * mt + 4 * g;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                v[e] = acc[mt][e] + (a.bias && oc0 + e < a.cout ? a.bias[oc0 + e] : 0.f);
+                if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
+            }
+            if (a.gate) {
+                const uint2 gv = *reinterpret_cast<const uint2*>(a.gate + p * 32 + oc0);
+                const uint16_t gs[4] = {(uint16_t)(gv.x & 0xffff), (uint16_t)(gv.x >> 16),
+                                        (uint16_t)(gv.y & 0xffff), (uint16_t)(gv.y >> 16)};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = (gs[e] != 0 && !(gs[e] & 0x8000)) ? v[e] : 0.f;   // gate > 0
+            }
+            if (a.y && oc0 < a.cout) {
+                uint2 o;
+                o.x = bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+                o.y = bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+                *reinterpret_cast<uint2*>(a.y + p * 32 + oc0) = o;
+            }
+            if (a.yf && mt == 0 && g == 0) a.yf[p] = v[0];
+        }
+    }
+}
+
+hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hipStream_t s)
+{
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, nframes);
+    if (cin == 32 && cout_pad == 32) hipLaunchKernelGGL((conv3x3_kernel<32, 2>), grid, dim3(256), 0, s, a);
+    else if (cin == 8 && cout_pad == 32) hipLaunchKernelGGL((conv3x3_kernel<8, 2>), grid, dim3(256), 0, s, a);
+    else if (cin == 32 && cout_pad == 16) hipLaunchKernelGGL((conv3x3_kernel<32, 1>), grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dgrad weights: Wt[tap][i][o] = W[8 - tap][o][i]  (the flipped tap set is
+// the mirrored 3x3 offset grid), zero-padded to the target shape.
+// ---------------------------------------------------------------------------
+__global__ void wtrans_kernel(const uint16_t* w, int oc_src, int ic_src, int oc_valid,
+                              uint16_t* wt, int oc_dst, int ic_dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * oc_dst * ic_dst) return;
+    const int tap = i / (oc_dst * ic_dst), r = i % (oc_dst * ic_dst);
+    const int o = r / ic_dst, in = r % ic_dst;   // o: input ch of the source layer
+    uint16_t v = 0;
+    if (in < oc_valid && o < ic_src) v = w[((8 - tap) * oc_src + in) * ic_src + o];
+    wt[i] = v;
+}
+
+hipError_t launch_wtrans(const uint16_t* w, int oc_src, int ic_src, int oc_valid, uint16_t* wt,
+                         int oc_dst, int ic_dst, hipStream_t s)
+{
+    const int n = 9 * oc_dst * ic_dst;
+    hipLaunchKernelGGL(wtrans_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, oc_src, ic_src,
+                       oc_valid, wt, oc_dst, ic_dst);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// wgrad: dW[tap][co][ci] = sum_p G[p][co] * X[p + off(tap)][ci], db[co] =
+// sum_p G[p][co], over the rows [y0, y0 + rows) of one frame; one partial
+// [9][32][32] + [32] per block, summed in a fixed order afterwards.
+// G^T and the shifted X^T tiles (64 pixels) are staged in LDS with padded
+// rows; wave w computes output tile (co-tile w / 2, ci-tile w % 2).
+// ---------------------------------------------------------------------------
+constexpr int kWgPx = 64, kWgLd = kWgPx + 8;
+
+template <int CIN, int GC>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
+{
+    __shared__ __align__(16) uint16_t gT[32][kWgLd];
+    __shared__ __align__(16) uint16_t xT[32][kWgLd];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int mt = wave >> 1, nt = wave & 1;
+    const int frame = blockIdx.y;
+    const int y0 = blockIdx.x * a.rows;
+    const uint16_t* X = a.x + (int64_t)frame * a.px_stride * CIN;
+    const uint16_t* G = a.g + (int64_t)frame * a.px_stride * GC;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    const bool active = (16 * mt < GC) && (16 * nt < CIN);
+    for (int y = y0; y < y0 + a.rows && y < a.H; ++y) {
+        for (int xb = 0; xb < a.W; xb += kWgPx) {
+            __syncthreads();
+            // stage G^T: 64 px x GC channels, 8 channels per 16-byte load
+            for (int i = threadIdx.x; i < kWgPx * (GC / 8); i += 256) {
+                const int pp = i / (GC / 8), c8 = i % (GC / 8);
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (xb + pp < a.W)
+                    v = *reinterpret_cast<const uint4*>(G + ((int64_t)y * a.W + xb + pp) * GC + 8 * c8);
+                const uint16_t e[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
+                                       (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16),
+                                       (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
+                                       (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) gT[8 * c8 + k][pp] = e[k];
+            }
+            __syncthreads();
+            if (threadIdx.x < GC) {
+                for (int pp = 0; pp < kWgPx; ++pp) bsum += bf16_f32(gT[threadIdx.x][pp]);
+            }
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dx = (tap % 3 - 1) * a.dil, dy = (tap / 3 - 1) * a.dil;
+                const int sy = y + dy;
+                for (int i = threadIdx.x; i < kWgPx * (CIN / 8); i += 256) {
+                    const int pp = i / (CIN / 8), c8 = i % (CIN / 8);
+                    const int sx = xb + pp + dx;
+                    uint4 v = make_uint4(0, 0, 0, 0);
+                    if (xb + pp < a.W && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
+                        v = *reinterpret_cast<const uint4*>(X + ((int64_t)sy * a.W + sx) * CIN + 8 * c8);
+                    const uint16_t e[8] = {(uint16_t)(v.x & 0xffff), (uint16_t)(v.x >> 16),
+                                           (uint16_t)(v.y & 0xffff), (uint16_t)(v.y >> 16),
+                                           (uint16_t)(v.z & 0xffff), (uint16_t)(v.z >> 16),
+                                           (uint16_t)(v.w & 0xffff), (uint16_t)(v.w >> 16)};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) xT[8 * c8 + k][pp] = e[k];
+                }
+                __syncthreads();
+                if (active) {
+#pragma unroll
+                    for (int ks = 0; ks < kWgPx / 32; ++ks) {
+                        const int co = 16 * mt + j, ci = 16 * nt + j;
+                        uint4 av = make_uint4(0, 0, 0, 0), bv = make_uint4(0, 0, 0, 0);
+                        if (co < GC) av = *reinterpret_cast<const uint4*>(&gT[co][32 * ks + 8 * g]);
+                        if (ci < CIN) bv = *reinterpret_cast<const uint4*>(&xT[ci][32 * ks + 8 * g]);
+                        acc[tap] = mfma16(av, bv, acc[tap]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // partial of this block: lane holds D[co = 16 mt + 4 g + e][ci = 16 nt + j]
+    float* pw = a.partial_w + (int64_t)(frame * gridDim.x + blockIdx.x) * 9 * 32 * 32;
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                pw[(t * 32 + 16 * mt + 4 * g + e) * 32 + 16 * nt + j] = acc[t][e];
+    } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                pw[(t * 32 + 16 * mt + 4 * g + e) * 32 + 16 * nt + j] = 0.f;
+    }
+    if (threadIdx.x < 32)
+        a.partial_b[(int64_t)(frame * gridDim.x + blockIdx.x) * 32 + threadIdx.x] =
+            threadIdx.x < GC ? bsum : 0.f;
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, int cin, int gc, int nframes, hipStream_t s)
+{
+    dim3 grid((a.H + a.rows - 1) / a.rows, nframes);
+    if (cin == 32 && gc == 32) hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(256), 0, s, a);
+    else if (cin == 8 && gc == 32) hipLaunchKernelGGL((wgrad_kernel<8, 32>), grid, dim3(256), 0, s, a);
+    else if (cin == 32 && gc == 8) hipLaunchKernelGGL((wgrad_kernel<32, 8>), grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Fixed-order sum of the per-block partials into the packed gradient of one
+// layer: gw[tap][oc][ic] (oc < oc_pad, ic < ic_n), gb[oc] (oc < oc_valid).
+__global__ void reduce_wgrad_kernel(const float* pw, const float* pb, int nblocks, int oc_pad,
+                                    int ic_n, int oc_valid, float* gw, float* gb)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = 9 * oc_pad * ic_n;
+    if (i < nw) {
+        const int tap = i / (oc_pad * ic_n), r = i % (oc_pad * ic_n);
+        const int oc = r / ic_n, ic = r % ic_n;
+        float s = 0.f;
+        if (oc < 32)
+            for (int b = 0; b < nblocks; ++b) s += pw[((int64_t)b * 9 + tap) * 1024 + oc * 32 + ic];
+        gw[i] = oc < oc_valid ? s : 0.f;
+    } else if (i < nw + oc_valid) {
+        const int oc = i - nw;
+        float s = 0.f;
+        for (int b = 0; b < nblocks; ++b) s += pb[(int64_t)b * 32 + oc];
+        gb[oc] = s;
+    }
+}
+
+hipError_t launch_reduce_wgrad(const float* pw, const float* pb, int nblocks, int oc_pad, int ic_n,
+                               int oc_valid, float* gw, float* gb, hipStream_t s)
+{
+    const int n = 9 * oc_pad * ic_n + oc_valid;
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3((n + 255) / 256), dim3(256), 0, s, pw, pb, nblocks,
+                       oc_pad, ic_n, oc_valid, gw, gb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Loss: binary cross-entropy with logits over the pixels the LiDAR test does
+// not decide (rho > Tc); the label is the plain check's mask.  Writes the
+// logit gradient (sigma(z) - y) * inv_n as the channel-0 of a bf16 [px][8]
+// map, and per-block partial sums (loss, count, agreement) in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void bce_kernel(LossArgs a)
+{
+    __shared__ float sl[256];
+    __shared__ int sc[256], sa[256];
+    const int frame = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float l = 0.f;
+    int c = 0, agree = 0;
+    if (i < a.px_stride) {
+        const int64_t p = (int64_t)frame * a.px_stride + i;
+        const float z = a.z[p];
+        const int lab = a.labels[p] ? 1 : 0;
+        const bool m = (int)a.rho[p] > a.tc;
+        float dz = 0.f;
+        if (m) {
+            const float sg = 1.f / (1.f + __expf(-z));
+            dz = (sg - (float)lab) * a.inv_n;
+            const float az = fabsf(z);
+            l = (z > 0.f ? z : 0.f) - z * (float)lab + log1pf(__expf(-az));
+            c = 1;
+            agree = ((z > 0.f) ? 1 : 0) == lab;
+        } else {
+            agree = lab;   // the LiDAR test decides; plain mask is valid too
+        }
+        uint4 o = make_uint4(bf16_rne(dz), 0, 0, 0);
+        *reinterpret_cast<uint4*>(a.dz + p * 8) = o;
+    }
+    sl[threadIdx.x] = l;
+    sc[threadIdx.x] = c;
+    sa[threadIdx.x] = i < a.px_stride ? agree : 0;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            sl[threadIdx.x] += sl[threadIdx.x + st];
+            sc[threadIdx.x] += sc[threadIdx.x + st];
+            sa[threadIdx.x] += sa[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t b = (int64_t)frame * gridDim.x + blockIdx.x;
+        a.partial_loss[b] = sl[0];
+        a.partial_cnt[b] = sc[0];
+        a.partial_agree[b] = sa[0];
+    }
+}
+
+__global__ void bce_reduce_kernel(const float* pl, const int* pc, const int* pa, int n, float* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float l = 0.f;
+    long long c = 0, ag = 0;
+    for (int i = 0; i < n; ++i) {
+        l += pl[i];
+        c += pc[i];
+        ag += pa[i];
+    }
+    out[0] = c ? l / (float)c : 0.f;   // mean loss over decided pixels
+    out[1] = (float)c;
+    out[2] = (float)ag;                // pixels where (z > 0 or LiDAR) == label
+}
+
+hipError_t launch_bce(const LossArgs& a, int nframes, hipStream_t s)
+{
+    const int nb = (int)((a.px_stride + 255) / 256);
+    hipLaunchKernelGGL(bce_kernel, dim3(nb, nframes), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.stats)
+        hipLaunchKernelGGL(bce_reduce_kernel, dim3(1), dim3(64), 0, s, a.partial_loss, a.partial_cnt,
+                           a.partial_agree, nb * nframes, a.stats);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the fp32 master parameters; writes the bf16 weights and fp32 biases
+// used by the kernels.  lr_t already carries the bias correction.
+// ---------------------------------------------------------------------------
+__global__ void adam_kernel(AdamArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float gr = a.grad[i];
+    const float m = a.b1 * a.m[i] + (1.f - a.b1) * gr;
+    const float v = a.b2 * a.v[i] + (1.f - a.b2) * gr * gr;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float p = a.master[i] - a.lr_t * m / (sqrtf(v) + a.eps);
+    a.master[i] = p;
+    if (i < a.n_w)
+        a.w_bf16[i] = bf16_rne(p);
+    else
+        a.bias[i - a.n_w] = p;
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Learned check output: valid = (logit > 0) or (rho <= Tc); counts the
+// undecided-and-uncertain pixels (rho > Tc, |logit| < margin) per frame for
+// the device-side fallback to the plain check.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void learned_mask_kernel(MaskArgs a)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int frame = blockIdx.z;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x < a.W && y < a.H) {
+        const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
+        const float z = a.logits[p];
+        const bool lid = (int)a.rho[p] <= a.tc;
+        const bool valid = lid || z > 0.f;
+        const int64_t o = (int64_t)frame * a.out_fstride + (int64_t)y * a.out_pitch + x;
+        a.valid_out[o] = valid ? 1 : 0;
+        a.disp_out[o] = valid ? a.dsub[p] : -1.0f;
+        if (!lid && fabsf(z) < a.margin) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(&a.counter[frame], cnt);
+}
+
+hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s)
+{
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, nframes);
+    hipLaunchKernelGGL(learned_mask_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace sldf

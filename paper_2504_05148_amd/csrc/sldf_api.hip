@@ -1,5 +1,6 @@
 // C ABI of libsldf.so: parameter validation, workspace plan and the launch
 // sequence of one frame batch (Fig. 1 flow of the paper).
+#include <math.h>
 #include <new>
 #include <string.h>
 
@@ -20,6 +21,8 @@ struct sldf_ctx {
     sldf_taps taps;
     int need_right;   // right-view pass needed (stereo half of the check)
     int n;            // census bits
+    const uint16_t* sur_w;  // learned-check parameters (caller-owned)
+    const float* sur_b;
     // timing
     hipEvent_t* events;
     int32_t timing_cap;     // runs that fit in events
@@ -60,7 +63,11 @@ sldf_status validate(const sldf_params* p)
     if (p->ts < 0 || p->ts > 64 || p->rs < 0 || p->rs > 15) return SLDF_EINVAL;
     if (p->tc < 0 || p->tc > 4096 || p->rc < 0 || p->rc > 31) return SLDF_EINVAL;
     if (p->check_mode < 0 || p->check_mode > 3) return SLDF_EINVAL;
-    if (p->check_impl != 0) return SLDF_EINVAL;
+    if (p->check_impl != 0 && p->check_impl != 1) return SLDF_EINVAL;
+    if (p->check_impl == 1 &&
+        (p->check_mode != 3 || !(p->fallback_tau >= 0.f && p->fallback_tau <= 1.f) ||
+         !(p->uncertain_margin >= 0.f)))
+        return SLDF_EINVAL;
     if (p->subpixel != 0 && p->subpixel != 1) return SLDF_EINVAL;
     if (p->batch < 1 || p->batch > 4096) return SLDF_EINVAL;
     // 16-bit bound: every L_r lies in [C', C' + P2'] (Eq. 2), the sum of the
@@ -74,6 +81,8 @@ sldf_status validate(const sldf_params* p)
     return SLDF_OK;
 }
 
+// right-view S volume: the plain stereo check, or the fallback of the
+// learned check
 bool needs_right(const sldf_params* p) { return p->check_mode == 1 || p->check_mode == 3; }
 
 // Workspace plan: one 256-byte aligned segment per array, each holding all
@@ -99,6 +108,15 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* dsub = seg(F * px * 4);
     void* sl = seg(F * cells * 2);
     void* sr = needs_right(p) ? seg(F * cells * 2) : nullptr;
+    void* rb = seg(F * px * (size_t)(p->max_disp / 32) * 4);
+    void* rho = seg(F * px * 2);
+    void* feat = seg(F * px * 8);
+    void* x0 = seg(F * px * 16);
+    const bool learned = p->check_impl == 1;
+    void* act0 = learned ? seg(F * px * 64) : nullptr;
+    void* act1 = learned ? seg(F * px * 64) : nullptr;
+    void* logits = learned ? seg(F * px * 4) : nullptr;
+    void* counter = learned ? seg(F * 4) : nullptr;
     if (b) {
         b->census_l = base ? (uint32_t*)cl + p->max_disp : nullptr;
         b->census_r = base ? (uint32_t*)cr + p->max_disp : nullptr;
@@ -110,6 +128,14 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->dsub = (float*)dsub;
         b->S_left = (uint16_t*)sl;
         b->S_right = (uint16_t*)sr;
+        b->rowbits = (uint32_t*)rb;
+        b->rho = (uint16_t*)rho;
+        b->feat = (uint32_t*)feat;
+        b->x0 = (uint16_t*)x0;
+        b->act[0] = (uint16_t*)act0;
+        b->act[1] = (uint16_t*)act1;
+        b->logits = (float*)logits;
+        b->counter = (int32_t*)counter;
         b->px_stride = (int64_t)px;
         b->S_stride = (int64_t)cells;
     }
@@ -169,6 +195,8 @@ void sldf_params_default(sldf_params* p)
     p->check_impl = 0;
     p->subpixel = 1;
     p->batch = 1;
+    p->fallback_tau = 0.05f;
+    p->uncertain_margin = 0.5f;
 }
 
 sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes)
@@ -299,6 +327,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (((uintptr_t)lidar & 1) != 0 || ((uintptr_t)disp_out & 3) != 0) return SLDF_EALIGN;
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) return SLDF_ESTATE;
+    const bool learned = p.check_impl == 1;
+    if (learned && (!ctx->sur_w || !ctx->sur_b)) return SLDF_ESTATE;
     hipStream_t s = (hipStream_t)hip_stream;
     const Buffers& b = ctx->buf;
     const int W = p.width, H = p.height, D = p.max_disp;
@@ -313,6 +343,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         return marks ? hipEventRecord(marks[k], s) : hipSuccess;
     };
     if (mark(0) != hipSuccess) return SLDF_EDEVICE;
+    if (learned && launch_fill_i32(b.counter, n_frames, 0, s) != hipSuccess) return SLDF_EDEVICE;
 
     // census of both images (Sec. IV-A)
     CensusArgs ca;
@@ -390,29 +421,58 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.p2s = (uint32_t)(p.alpha_den * p.p2);
     ga.subpixel = p.subpixel;
     ga.store_sum = ctx->taps.cost_sum != nullptr;
-    const int nviews = ctx->need_right ? 2 : 1;
-    for (int r = 0; r < p.num_paths; ++r) {
-        ga.dx = kDirs[r][0];
-        ga.dy = kDirs[r][1];
-        ga.nlines = num_lines(W, H, ga.dx, ga.dy);
-        int mode = p.num_paths == 1 ? kSingle
-                   : r == 0          ? kFirst
-                   : r == p.num_paths - 1 ? kLast
-                                     : kMiddle;
-        if ((e = launch_sgm_dir(ga, D, mode, nviews, n_frames, s)) != hipSuccess)
-            return SLDF_EDEVICE;
-        ctx->launches[2] += 1;
-    }
+    const bool want_features = learned || ctx->taps.features != nullptr;
+    ga.feat = want_features ? b.feat : nullptr;
+    // plain check: both views in every launch; learned check: left view
+    // here, right view only in the gated fallback below
+    const int nviews = ctx->need_right && !learned ? 2 : 1;
+    auto sgm_passes = [&](int view_base, int nv, int stage) {
+        ga.view_base = view_base;
+        for (int r = 0; r < p.num_paths; ++r) {
+            ga.dx = kDirs[r][0];
+            ga.dy = kDirs[r][1];
+            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+            int mode = p.num_paths == 1 ? kSingle
+                       : r == 0          ? kFirst
+                       : r == p.num_paths - 1 ? kLast
+                                         : kMiddle;
+            if (launch_sgm_dir(ga, D, mode, nv, n_frames, s) != hipSuccess) return false;
+            ctx->launches[stage] += 1;
+        }
+        return true;
+    };
+    if (!sgm_passes(0, nviews, 2)) return SLDF_EDEVICE;
     if (mark(3) != hipSuccess) return SLDF_EDEVICE;
+
+    // LiDAR window masks and residual (the LiDAR half of Eq. 6), surrogate
+    // inputs when requested
+    LidarArgs la;
+    la.lidar = lidar;
+    la.lidar_pitch = lidar_pitch;
+    la.lidar_fstride = lidar_frame_stride;
+    la.rowbits = b.rowbits;
+    la.dstar = b.dstar;
+    la.rho = b.rho;
+    la.feat = b.feat;
+    la.x0 = want_features ? b.x0 : nullptr;
+    la.px_stride = b.px_stride;
+    la.W = W;
+    la.H = H;
+    la.D = D;
+    la.rc = p.rc;
+    la.sS = 1.0f / (float)(p.num_paths * p.alpha_den * p.p2);
+    la.sD = 1.0f / (float)D;
+    la.sR = 1.0f / 32.0f;
+    if ((e = launch_lidar_bits(la, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
 
     // stereo-LiDAR consistency check (Sec. IV-C, Eq. 6)
     CheckArgs ka;
+    ka.gate = nullptr;
+    ka.gate_limit = 0;
     ka.dstar = b.dstar;
     ka.dright = b.dright;
     ka.dsub = b.dsub;
-    ka.lidar = lidar;
-    ka.lidar_pitch = lidar_pitch;
-    ka.lidar_fstride = lidar_frame_stride;
+    ka.rho = b.rho;
     ka.disp_out = disp_out;
     ka.valid_out = valid_out;
     ka.out_pitch = out_pitch;
@@ -423,9 +483,64 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ka.tc = p.tc;
     ka.rc = p.rc;
     ka.mode = p.check_mode;
-    if ((e = launch_check(ka, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
-    if (mark(4) != hipSuccess) return SLDF_EDEVICE;
-    ctx->launches[3] += 1;
+    if (!learned) {
+        if ((e = launch_check(ka, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
+        ctx->launches[3] += 1;
+        if (mark(4) != hipSuccess || mark(5) != hipSuccess) return SLDF_EDEVICE;
+    } else {
+        // learned check: CNN on the surrogate inputs, then the mask
+        const uint16_t* w = ctx->sur_w;
+        const float* bb = ctx->sur_b;
+        const uint16_t* in = b.x0;
+        for (int l = 0; l < 4; ++l) {
+            ConvArgs cv;
+            cv.x = in;
+            cv.w = w + (l == 0 ? kSurOffW1 : l == 1 ? kSurOffW2 : l == 2 ? kSurOffW3 : kSurOffW4);
+            cv.bias = bb + (l == 0 ? kSurOffB1 : l == 1 ? kSurOffB2 : l == 2 ? kSurOffB3 : kSurOffB4);
+            cv.y = l < 3 ? b.act[l & 1] : nullptr;
+            cv.yf = l == 3 ? b.logits : nullptr;
+            cv.gate = nullptr;
+            cv.px_stride = b.px_stride;
+            cv.W = W;
+            cv.H = H;
+            cv.dil = kSurDil[l];
+            cv.relu = l < 3;
+            cv.cout = l < 3 ? 32 : 1;
+            if (launch_conv(cv, l == 0 ? 8 : 32, l < 3 ? 32 : 16, n_frames, s) != hipSuccess)
+                return SLDF_EDEVICE;
+            in = b.act[l & 1];
+        }
+        MaskArgs ma;
+        ma.logits = b.logits;
+        ma.rho = b.rho;
+        ma.dsub = b.dsub;
+        ma.disp_out = disp_out;
+        ma.valid_out = valid_out;
+        ma.counter = b.counter;
+        ma.px_stride = b.px_stride;
+        ma.out_pitch = out_pitch;
+        ma.out_fstride = out_frame_stride;
+        ma.W = W;
+        ma.H = H;
+        ma.tc = p.tc;
+        ma.margin = p.uncertain_margin;
+        if (launch_learned_mask(ma, n_frames, s) != hipSuccess) return SLDF_EDEVICE;
+        ctx->launches[3] += 5;
+        if (mark(4) != hipSuccess) return SLDF_EDEVICE;
+        // fallback: frames with too many uncertain pixels run the right-view
+        // SGM and the plain check (every block tests the device counter)
+        const int32_t limit = (int32_t)(p.fallback_tau * (float)W * (float)H);
+        ga.gate = b.counter;
+        ga.gate_limit = limit;
+        ga.feat = nullptr;
+        ga.store_sum = 0;
+        if (!sgm_passes(1, 1, 4)) return SLDF_EDEVICE;
+        ka.gate = b.counter;
+        ka.gate_limit = limit;
+        if ((e = launch_check(ka, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
+        ctx->launches[4] += 1;
+        if (mark(5) != hipSuccess) return SLDF_EDEVICE;
+    }
 
     // debug taps of frame 0
     const sldf_taps& t = ctx->taps;
@@ -446,6 +561,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         return SLDF_EDEVICE;
     if (t.dright && ctx->need_right && cp(t.dright, b.dright, px * 2) != hipSuccess)
         return SLDF_EDEVICE;
+    if (cp(t.rho, b.rho, px * 2) != hipSuccess || cp(t.features, b.x0, px * 16) != hipSuccess)
+        return SLDF_EDEVICE;
     if (t.prior) {
         if (p.semidense) {
             if (cp(t.prior, b.prior, px * 2) != hipSuccess) return SLDF_EDEVICE;
@@ -464,6 +581,241 @@ sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
 {
     return sldf_run_batch(ctx, 1, left, right, img_pitch, 0, lidar, lidar_pitch, 0,
                           disp_out, valid_out, out_pitch, 0, hip_stream);
+}
+
+int32_t sldf_surrogate_num_weights(void) { return kSurNW; }
+int32_t sldf_surrogate_num_biases(void) { return kSurNB; }
+
+sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
+                                       const float* biases)
+{
+    if (!ctx || (!weights) != (!biases)) return SLDF_EINVAL;
+    ctx->sur_w = weights;
+    ctx->sur_b = biases;
+    return SLDF_OK;
+}
+
+namespace {
+
+hipError_t surrogate_forward(const uint16_t* x0, int W, int H, int F, const uint16_t* w,
+                             const float* bb, uint16_t* const act[3], float* logits,
+                             hipStream_t s)
+{
+    const uint16_t* in = x0;
+    for (int l = 0; l < 4; ++l) {
+        ConvArgs cv;
+        cv.x = in;
+        cv.w = w + (l == 0 ? kSurOffW1 : l == 1 ? kSurOffW2 : l == 2 ? kSurOffW3 : kSurOffW4);
+        cv.bias = bb + (l == 0 ? kSurOffB1 : l == 1 ? kSurOffB2 : l == 2 ? kSurOffB3 : kSurOffB4);
+        cv.y = l < 3 ? act[l] : nullptr;
+        cv.yf = l == 3 ? logits : nullptr;
+        cv.gate = nullptr;
+        cv.px_stride = (int64_t)W * H;
+        cv.W = W;
+        cv.H = H;
+        cv.dil = kSurDil[l];
+        cv.relu = l < 3;
+        cv.cout = l < 3 ? 32 : 1;
+        hipError_t e = launch_conv(cv, l == 0 ? 8 : 32, l < 3 ? 32 : 16, F, s);
+        if (e != hipSuccess) return e;
+        if (l < 3) in = act[l];
+    }
+    return hipSuccess;
+}
+
+constexpr int kWgRows = 8;
+
+// training workspace plan (byte offsets, 256-aligned)
+struct TrainPlan {
+    size_t a1, a2, a3, z, dz, d3, d2, d1, wt4, wt3, wt2, pw, pb, grads, pl, pc, pa, stats, total;
+};
+
+TrainPlan train_plan(int W, int H, int F)
+{
+    TrainPlan t;
+    const size_t px = (size_t)W * H * F;
+    const size_t wblocks = (size_t)F * ((H + kWgRows - 1) / kWgRows);
+    const size_t lblocks = (size_t)F * (((size_t)W * H + 255) / 256);
+    size_t off = 0;
+    auto seg = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    t.a1 = seg(px * 64);
+    t.a2 = seg(px * 64);
+    t.a3 = seg(px * 64);
+    t.z = seg(px * 4);
+    t.dz = seg(px * 16);
+    t.d3 = seg(px * 64);
+    t.d2 = seg(px * 64);
+    t.d1 = seg(px * 64);
+    t.wt4 = seg(9 * 32 * 8 * 2);
+    t.wt3 = seg(9 * 32 * 32 * 2);
+    t.wt2 = seg(9 * 32 * 32 * 2);
+    t.pw = seg(wblocks * 9 * 32 * 32 * 4);
+    t.pb = seg(wblocks * 32 * 4);
+    t.grads = seg((size_t)(kSurNW + kSurNB) * 4);
+    t.pl = seg(lblocks * 4);
+    t.pc = seg(lblocks * 4);
+    t.pa = seg(lblocks * 4);
+    t.stats = seg(16);
+    t.total = off;
+    return t;
+}
+
+}  // namespace
+
+sldf_status sldf_surrogate_forward(const uint16_t* x0, int32_t width, int32_t height,
+                                   int32_t n_frames, const uint16_t* weights,
+                                   const float* biases, uint16_t* act1, uint16_t* act2,
+                                   uint16_t* act3, float* logits, void* hip_stream)
+{
+    if (!x0 || !weights || !biases || !act1 || !act2 || !act3 || !logits || width < 1 ||
+        height < 1 || n_frames < 1)
+        return SLDF_EINVAL;
+    if ((((uintptr_t)x0 | (uintptr_t)act1 | (uintptr_t)act2 | (uintptr_t)act3 |
+          (uintptr_t)weights) & 15) != 0)
+        return SLDF_EALIGN;
+    uint16_t* const act[3] = {act1, act2, act3};
+    return surrogate_forward(x0, width, height, n_frames, weights, biases, act, logits,
+                             (hipStream_t)hip_stream) == hipSuccess
+               ? SLDF_OK
+               : SLDF_EDEVICE;
+}
+
+sldf_status sldf_surrogate_train_workspace_size(int32_t width, int32_t height,
+                                                int32_t n_frames, size_t* bytes)
+{
+    if (!bytes || width < 1 || height < 1 || n_frames < 1) return SLDF_EINVAL;
+    *bytes = train_plan(width, height, n_frames).total;
+    return SLDF_OK;
+}
+
+sldf_status sldf_surrogate_train_step(const uint16_t* x0, const uint8_t* labels,
+                                      const uint16_t* rho, int32_t tc, int32_t width,
+                                      int32_t height, int32_t n_frames, float* master,
+                                      float* adam_m, float* adam_v, uint16_t* weights,
+                                      float* biases, float lr, float beta1, float beta2,
+                                      float eps, int32_t step, int32_t apply_update,
+                                      void* workspace, size_t ws_bytes, float* grads_out,
+                                      float* stats_out, void* hip_stream)
+{
+    if (!x0 || !labels || !rho || !master || !adam_m || !adam_v || !weights || !biases ||
+        !workspace || width < 1 || height < 1 || n_frames < 1 || step < 1)
+        return SLDF_EINVAL;
+    if ((((uintptr_t)x0 | (uintptr_t)weights | (uintptr_t)workspace) & 15) != 0)
+        return SLDF_EALIGN;
+    const int W = width, H = height, F = n_frames;
+    const TrainPlan tp = train_plan(W, H, F);
+    if (ws_bytes < tp.total) return SLDF_ENOMEM;
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* ws = (char*)workspace;
+    uint16_t* a1 = (uint16_t*)(ws + tp.a1);
+    uint16_t* a2 = (uint16_t*)(ws + tp.a2);
+    uint16_t* a3 = (uint16_t*)(ws + tp.a3);
+    float* z = (float*)(ws + tp.z);
+    uint16_t* dz = (uint16_t*)(ws + tp.dz);
+    uint16_t* d3 = (uint16_t*)(ws + tp.d3);
+    uint16_t* d2 = (uint16_t*)(ws + tp.d2);
+    uint16_t* d1 = (uint16_t*)(ws + tp.d1);
+    uint16_t* wt4 = (uint16_t*)(ws + tp.wt4);
+    uint16_t* wt3 = (uint16_t*)(ws + tp.wt3);
+    uint16_t* wt2 = (uint16_t*)(ws + tp.wt2);
+    float* pw = (float*)(ws + tp.pw);
+    float* pb = (float*)(ws + tp.pb);
+    float* grads = (float*)(ws + tp.grads);
+    const int64_t pxs = (int64_t)W * H;
+    uint16_t* const act[3] = {a1, a2, a3};
+    if (surrogate_forward(x0, W, H, F, weights, biases, act, z, s) != hipSuccess)
+        return SLDF_EDEVICE;
+
+    LossArgs la;
+    la.z = z;
+    la.labels = labels;
+    la.rho = rho;
+    la.dz = dz;
+    la.partial_loss = (float*)(ws + tp.pl);
+    la.partial_cnt = (int32_t*)(ws + tp.pc);
+    la.partial_agree = (int32_t*)(ws + tp.pa);
+    la.stats = stats_out;
+    la.px_stride = pxs;
+    la.tc = tc;
+    la.inv_n = 1.0f / (float)(pxs * F);
+    if (launch_bce(la, F, s) != hipSuccess) return SLDF_EDEVICE;
+
+    // dgrad weights from the current (bf16) weights
+    if (launch_wtrans(weights + kSurOffW4, 16, 32, 1, wt4, 32, 8, s) != hipSuccess ||
+        launch_wtrans(weights + kSurOffW3, 32, 32, 32, wt3, 32, 32, s) != hipSuccess ||
+        launch_wtrans(weights + kSurOffW2, 32, 32, 32, wt2, 32, 32, s) != hipSuccess)
+        return SLDF_EDEVICE;
+
+    const int nwb = (H + kWgRows - 1) / kWgRows;
+    auto wgrad = [&](const uint16_t* xin, int cin, const uint16_t* g, int gc, int dil,
+                     int oc_pad, int oc_valid, int woff, int boff) {
+        WgradArgs wa;
+        wa.x = xin;
+        wa.g = g;
+        wa.partial_w = pw;
+        wa.partial_b = pb;
+        wa.px_stride = pxs;
+        wa.W = W;
+        wa.H = H;
+        wa.dil = dil;
+        wa.rows = kWgRows;
+        if (launch_wgrad(wa, cin, gc, F, s) != hipSuccess) return false;
+        return launch_reduce_wgrad(pw, pb, nwb * F, oc_pad, cin, oc_valid, grads + woff,
+                                   grads + kSurNW + boff, s) == hipSuccess;
+    };
+    auto dgrad = [&](const uint16_t* g, int gc, const uint16_t* wt, const uint16_t* gate,
+                     int dil, uint16_t* out) {
+        ConvArgs cv;
+        cv.x = g;
+        cv.w = wt;
+        cv.bias = nullptr;
+        cv.y = out;
+        cv.yf = nullptr;
+        cv.gate = gate;
+        cv.px_stride = pxs;
+        cv.W = W;
+        cv.H = H;
+        cv.dil = dil;
+        cv.relu = 0;
+        cv.cout = 32;
+        return launch_conv(cv, gc, 32, F, s) == hipSuccess;
+    };
+    // layer 4 (32 -> 1, dilation 8), layer 3, layer 2, layer 1
+    if (!wgrad(a3, 32, dz, 8, kSurDil[3], 16, 1, kSurOffW4, kSurOffB4) ||
+        !dgrad(dz, 8, wt4, a3, kSurDil[3], d3) ||
+        !wgrad(a2, 32, d3, 32, kSurDil[2], 32, 32, kSurOffW3, kSurOffB3) ||
+        !dgrad(d3, 32, wt3, a2, kSurDil[2], d2) ||
+        !wgrad(a1, 32, d2, 32, kSurDil[1], 32, 32, kSurOffW2, kSurOffB2) ||
+        !dgrad(d2, 32, wt2, a1, kSurDil[1], d1) ||
+        !wgrad(x0, 8, d1, 32, kSurDil[0], 32, 32, kSurOffW1, kSurOffB1))
+        return SLDF_EDEVICE;
+    if (grads_out &&
+        hipMemcpyAsync(grads_out, grads, (size_t)(kSurNW + kSurNB) * 4, hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+        return SLDF_EDEVICE;
+    if (apply_update) {
+        AdamArgs aa;
+        aa.master = master;
+        aa.m = adam_m;
+        aa.v = adam_v;
+        aa.grad = grads;
+        aa.w_bf16 = weights;
+        aa.bias = biases;
+        aa.n = kSurNW + kSurNB;
+        aa.n_w = kSurNW;
+        aa.b1 = beta1;
+        aa.b2 = beta2;
+        aa.eps = eps;
+        const double bc1 = 1.0 - pow((double)beta1, (double)step);
+        const double bc2 = 1.0 - pow((double)beta2, (double)step);
+        aa.lr_t = (float)((double)lr * sqrt(bc2) / bc1);
+        if (launch_adam(aa, s) != hipSuccess) return SLDF_EDEVICE;
+    }
+    return SLDF_OK;
 }
 
 sldf_status sldf_lidar_quantize(const float* in, int32_t width, int32_t height,

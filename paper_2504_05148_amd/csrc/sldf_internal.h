@@ -23,6 +23,13 @@ struct Buffers {
     float* dsub;          // [F][H][W]
     uint16_t* S_left;     // [F][H][W][D]
     uint16_t* S_right;    // [F][H][W][D] (only when the stereo check is on)
+    uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
+    uint16_t* rho;        // [F][H][W] LiDAR residual
+    uint32_t* feat;       // [F][H][W][2] surrogate cost features
+    uint16_t* x0;         // [F][H][W][8] bf16 surrogate inputs
+    uint16_t* act[2];     // [F][H][W][32] bf16 CNN activations (learned check)
+    float* logits;        // [F][H][W] (learned check)
+    int32_t* counter;     // [F] uncertain pixels per frame (learned check)
     int64_t px_stride;    // W * H
     int64_t S_stride;     // W * H * D
 };
@@ -75,19 +82,38 @@ struct SgmArgs {
     uint32_t p1s, p2s;          // den * P1, den * P2
     int32_t subpixel;
     int32_t store_sum;          // last pass also stores S (debug tap)
+    uint32_t* feat;             // last left pass: surrogate cost features, or null
+    // fallback gate: when non-null, frame f runs only if gate[f] > gate_limit
+    const int32_t* gate;
+    int32_t gate_limit;
+    int32_t view_base;          // first view of the launch (1 = right view only)
     // launch geometry (filled by launch_sgm_dir)
     int32_t blocks_per_fv;      // blocks per (frame, view)
     int32_t nviews;
     int32_t n_fv;               // frames * views
 };
 
+struct LidarArgs {
+    const int16_t* lidar;       // raw sparse map D-bar
+    int32_t lidar_pitch;
+    int64_t lidar_fstride;
+    uint32_t* rowbits;          // [F][H][W][D / 32] row-pass masks
+    const int16_t* dstar;       // [F][H][W]
+    uint16_t* rho;              // [F][H][W] LiDAR residual (65535 = none)
+    const uint32_t* feat;       // [F][H][W][2] (S(d*) | S2nd << 16, curvature)
+    uint16_t* x0;               // [F][H][W][8] bf16 surrogate inputs, or null
+    int64_t px_stride;
+    int32_t W, H, D, rc;
+    float sS, sD, sR;           // feature scales
+};
+
 struct CheckArgs {
+    const int32_t* gate;        // when non-null, frame f runs only if gate[f] > gate_limit
+    int32_t gate_limit;
     const int16_t* dstar;
     const int16_t* dright;
     const float* dsub;
-    const int16_t* lidar;
-    int32_t lidar_pitch;
-    int64_t lidar_fstride;
+    const uint16_t* rho;        // LiDAR residual (Eq. 6 LiDAR test: rho <= Tc)
     float* disp_out;
     uint8_t* valid_out;
     int32_t out_pitch;
@@ -96,6 +122,86 @@ struct CheckArgs {
     int32_t W, H, tc, rc, mode;
 };
 
+// ---- learned consistency surrogate ----
+// Packed parameters: bf16 weights [tap][out][in] per layer, then fp32 biases.
+constexpr int kSurCh = 32;
+constexpr int kSurW1 = 9 * 32 * 8, kSurW2 = 9 * 32 * 32, kSurW3 = 9 * 32 * 32, kSurW4 = 9 * 16 * 32;
+constexpr int kSurOffW1 = 0, kSurOffW2 = kSurW1, kSurOffW3 = kSurOffW2 + kSurW2,
+              kSurOffW4 = kSurOffW3 + kSurW3, kSurNW = kSurOffW4 + kSurW4;
+constexpr int kSurNB = 32 + 32 + 32 + 1;
+constexpr int kSurOffB1 = 0, kSurOffB2 = 32, kSurOffB3 = 64, kSurOffB4 = 96;
+constexpr int kSurDil[4] = {1, 2, 4, 8};
+
+struct ConvArgs {
+    const uint16_t* x;        // NHWC bf16 input [F][H][W][cin]
+    const uint16_t* w;        // [9][cout_pad][cin] bf16
+    const float* bias;        // [cout] or null
+    uint16_t* y;              // NHWC bf16 output [F][H][W][32] or null
+    float* yf;                // channel-0 fp32 output [F][H][W] or null
+    const uint16_t* gate;     // NHWC bf16 [F][H][W][32]: keep output where gate > 0
+    int64_t px_stride;
+    int32_t W, H, dil, relu, cout;
+};
+
+struct WgradArgs {
+    const uint16_t* x;        // layer input NHWC [F][H][W][cin]
+    const uint16_t* g;        // output gradient NHWC [F][H][W][gc]
+    float* partial_w;         // [F * blocks][9][32][32]
+    float* partial_b;         // [F * blocks][32]
+    int64_t px_stride;
+    int32_t W, H, dil, rows;
+};
+
+struct LossArgs {
+    const float* z;           // logits [F][H][W]
+    const uint8_t* labels;    // plain-check mask [F][H][W]
+    const uint16_t* rho;      // LiDAR residual [F][H][W]
+    uint16_t* dz;             // [F][H][W][8] bf16, channel 0 = dLoss/dz
+    float* partial_loss;
+    int32_t* partial_cnt;
+    int32_t* partial_agree;
+    float* stats;             // [3]: mean loss, decided pixels, agreeing pixels
+    int64_t px_stride;
+    int32_t tc;
+    float inv_n;
+};
+
+struct AdamArgs {
+    float* master;
+    float* m;
+    float* v;
+    const float* grad;
+    uint16_t* w_bf16;
+    float* bias;
+    int32_t n, n_w;
+    float b1, b2, eps, lr_t;
+};
+
+struct MaskArgs {
+    const float* logits;
+    const uint16_t* rho;
+    const float* dsub;
+    float* disp_out;
+    uint8_t* valid_out;
+    int32_t* counter;         // [F] uncertain pixels per frame
+    int64_t px_stride;
+    int32_t out_pitch;
+    int64_t out_fstride;
+    int32_t W, H, tc;
+    float margin;
+};
+
+hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hipStream_t s);
+hipError_t launch_wtrans(const uint16_t* w, int oc_src, int ic_src, int oc_valid, uint16_t* wt,
+                         int oc_dst, int ic_dst, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, int cin, int gc, int nframes, hipStream_t s);
+hipError_t launch_reduce_wgrad(const float* pw, const float* pb, int nblocks, int oc_pad, int ic_n,
+                               int oc_valid, float* gw, float* gb, hipStream_t s);
+hipError_t launch_bce(const LossArgs& a, int nframes, hipStream_t s);
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
+hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s);
+
 enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2, kSingle = 3 };
 
 hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s);
@@ -103,6 +209,7 @@ hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
 hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s);
+hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s);
 hipError_t launch_quantize(const float* in, int W, int H, int in_pitch, int D,
                            int16_t* out, int out_pitch, hipStream_t s);
 

@@ -24,16 +24,21 @@ _PARAM_FIELDS = ("struct_size", "width", "height", "max_disp", "census_w", "cens
                  "check_impl", "subpixel", "batch")
 
 
+_PARAM_FLOATS = ("fallback_tau", "uncertain_margin")
+
+
 class Params(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int32) for k in _PARAM_FIELDS]
+    _fields_ = ([(k, ctypes.c_int32) for k in _PARAM_FIELDS] +
+                [(k, ctypes.c_float) for k in _PARAM_FLOATS])
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in _PARAM_FIELDS}
+        return {k: getattr(self, k) for k in _PARAM_FIELDS + _PARAM_FLOATS}
 
 
 class Taps(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in
-                ("census_l", "census_r", "prior", "cost_sum", "dstar", "dright", "dsub")]
+                ("census_l", "census_r", "prior", "cost_sum", "dstar", "dright", "dsub",
+                 "rho", "features")]
 
 
 class SldfError(RuntimeError):
@@ -70,9 +75,22 @@ def lib():
         L.sldf_timing_enable.argtypes = [_vp, _i32]
         L.sldf_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+        L.sldf_surrogate_num_weights.restype = _i32
+        L.sldf_surrogate_num_biases.restype = _i32
+        L.sldf_surrogate_set_weights.argtypes = [_vp, _vp, _vp]
+        L.sldf_surrogate_forward.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                             _vp, _vp]
+        L.sldf_surrogate_train_workspace_size.argtypes = [_i32, _i32, _i32,
+                                                          ctypes.POINTER(_sz)]
+        _f = ctypes.c_float
+        L.sldf_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp,
+                                                _vp, _vp, _vp, _vp, _f, _f, _f, _f, _i32,
+                                                _i32, _vp, _sz, _vp, _vp, _vp]
         for f in ("sldf_workspace_size", "sldf_create", "sldf_destroy", "sldf_set_taps",
                   "sldf_run", "sldf_run_batch", "sldf_lidar_quantize",
-                  "sldf_timing_enable", "sldf_timing_read"):
+                  "sldf_timing_enable", "sldf_timing_read", "sldf_surrogate_set_weights",
+                  "sldf_surrogate_forward", "sldf_surrogate_train_workspace_size",
+                  "sldf_surrogate_train_step"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -91,9 +109,12 @@ def default_params(**overrides) -> Params:
     p = Params()
     lib().sldf_params_default(ctypes.byref(p))
     for k, v in overrides.items():
-        if k not in _PARAM_FIELDS:
+        if k in _PARAM_FIELDS:
+            setattr(p, k, int(v))
+        elif k in _PARAM_FLOATS:
+            setattr(p, k, float(v))
+        else:
             raise KeyError(k)
-        setattr(p, k, int(v))
     return p
 
 
@@ -181,22 +202,31 @@ class Context:
 
     def set_taps(self, **tensors):
         """Debug taps (frame 0): census_l, census_r, prior, cost_sum, dstar,
-        dright, dsub -> device tensors of the documented dtypes."""
+        dright, dsub, rho, features -> device tensors of the documented
+        dtypes."""
         t = Taps()
         for k, v in tensors.items():
             setattr(t, k, _ptr(v) if v is not None else None)
         self._taps_keep = dict(tensors)
         _check(lib().sldf_set_taps(self._h, ctypes.byref(t)), "sldf_set_taps")
 
-    STAGES = ("census", "semidense", "sgm", "check")
+    STAGES = ("census", "semidense", "sgm", "check", "fallback")
 
     def timing_enable(self, max_runs: int):
         _check(lib().sldf_timing_enable(self._h, int(max_runs)), "sldf_timing_enable")
 
+    def set_surrogate(self, weights: torch.Tensor | None, biases: torch.Tensor | None):
+        """Attach learned-check parameters (device tensors: int16/uint16
+        bf16 bit patterns and float32); they are referenced, not copied."""
+        self._sur_keep = (weights, biases)
+        _check(lib().sldf_surrogate_set_weights(
+            self._h, _ptr(weights) if weights is not None else None,
+            _ptr(biases) if biases is not None else None), "sldf_surrogate_set_weights")
+
     def timing_read(self):
         """{stage: (total_ms, launches)} since the last read (waits on events)."""
-        ms = (ctypes.c_double * 4)()
-        n = (ctypes.c_int64 * 4)()
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_int64 * 5)()
         _check(lib().sldf_timing_read(self._h, ms, n), "sldf_timing_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(self.STAGES)}
 
@@ -233,3 +263,70 @@ class Context:
                                     disp.stride(0), _stream_handle(stream)),
                "sldf_run_batch")
         return disp, valid
+
+
+# ---------------------------------------------------------------- surrogate --
+def surrogate_sizes():
+    return int(lib().sldf_surrogate_num_weights()), int(lib().sldf_surrogate_num_biases())
+
+
+def surrogate_forward(x0: torch.Tensor, weights: torch.Tensor, biases: torch.Tensor,
+                      stream=None):
+    """x0 bf16-bits [F, H, W, 8] (int16) -> (logits [F, H, W] f32, (a1, a2, a3))."""
+    F, H, W, C = x0.shape
+    assert C == 8 and x0.is_contiguous()
+    acts = [torch.empty((F, H, W, 32), dtype=torch.int16, device=x0.device) for _ in range(3)]
+    z = torch.empty((F, H, W), dtype=torch.float32, device=x0.device)
+    _check(lib().sldf_surrogate_forward(_ptr(x0), W, H, F, _ptr(weights), _ptr(biases),
+                                        _ptr(acts[0]), _ptr(acts[1]), _ptr(acts[2]), _ptr(z),
+                                        _stream_handle(stream)), "sldf_surrogate_forward")
+    return z, acts
+
+
+class SurrogateTrainer:
+    """Adam training of the learned check through sldf_surrogate_train_step
+    (fp32 master parameters, bf16 working weights)."""
+
+    def __init__(self, W, H, F, master: torch.Tensor, device="cuda", lr=1e-3, betas=(0.9, 0.999),
+                 eps=1e-8):
+        nw, nb = surrogate_sizes()
+        assert master.numel() == nw + nb and master.dtype == torch.float32
+        self.W, self.H, self.F = W, H, F
+        self.master = master.to(device).contiguous()
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.nw, self.nb = nw, nb
+        self.weights = torch.empty(nw, dtype=torch.int16, device=device)
+        self.biases = torch.empty(nb, dtype=torch.float32, device=device)
+        self.sync_working()
+        n = _sz()
+        _check(lib().sldf_surrogate_train_workspace_size(W, H, F, ctypes.byref(n)),
+               "sldf_surrogate_train_workspace_size")
+        self.ws = torch.empty(int(n.value) + 256, dtype=torch.uint8, device=device)
+        off = (-_ptr(self.ws)) % 256
+        self._ws = self.ws[off:off + int(n.value)]
+        self.ws_bytes = int(n.value)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.step_count = 0
+        self.stats = torch.zeros(4, dtype=torch.float32, device=device)
+
+    def sync_working(self):
+        """bf16 (round to nearest even) working weights from the master copy."""
+        w = self.master[:self.nw]
+        u = w.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+        self.weights.copy_(u.to(torch.int32).to(torch.int16))
+        self.biases.copy_(self.master[self.nw:])
+
+    def step(self, x0, labels, rho, tc, update=True, grads_out=None, stream=None):
+        F = x0.shape[0]
+        assert F <= self.F
+        if update:
+            self.step_count += 1
+        _check(lib().sldf_surrogate_train_step(
+            _ptr(x0), _ptr(labels), _ptr(rho), int(tc), self.W, self.H, F, _ptr(self.master),
+            _ptr(self.m), _ptr(self.v), _ptr(self.weights), _ptr(self.biases), self.lr,
+            self.betas[0], self.betas[1], self.eps, max(self.step_count, 1), int(update),
+            _ptr(self._ws), self.ws_bytes, _ptr(grads_out) if grads_out is not None else None,
+            _ptr(self.stats), _stream_handle(stream)), "sldf_surrogate_train_step")
+        return self.stats

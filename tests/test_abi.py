@@ -48,12 +48,15 @@ def test_params_default_is_tab2():
 def test_workspace_size_plan():
     p = sldf.default_params()
     n1 = sldf.workspace_size(p)
-    px, cells = 1242 * 375, 1242 * 375 * 128
-    # census x2 (u32), prior, d*, d' (i16), dsub (f32), S left + right (u16)
-    assert n1 >= px * (4 + 4 + 2 + 2 + 2 + 4) + 2 * cells * 2
-    assert n1 < px * (4 + 4 + 2 + 2 + 2 + 4) + 2 * cells * 2 + 8 * 256
+    W, H, D = 1242, 375, 128
+    px, cells = W * H, W * H * D
+    census = 2 * (W + 2 * D) * H * 4            # padded census rows, both views
+    # prior, d*, d' (i16), dsub (f32), S left + right (u16), LiDAR row masks
+    # (D/32 words), rho (u16), cost features (2 u32), surrogate inputs (8 bf16)
+    exact = census + px * (2 + 2 + 2 + 4) + 2 * cells * 2 + px * (D // 32 * 4 + 2 + 8 + 16)
+    assert exact <= n1 < exact + 16 * 256
     p.batch = 4
-    assert sldf.workspace_size(p) >= 4 * (n1 - 8 * 256)
+    assert 4 * exact <= sldf.workspace_size(p) < 4 * exact + 16 * 256
     p = sldf.default_params(check_mode=2)      # no right-view pass: one S volume
     assert sldf.workspace_size(p) < n1 - cells
 

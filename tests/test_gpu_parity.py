@@ -48,7 +48,9 @@ def run_gpu(frame, pkw, taps=True):
                  cost_sum=torch.empty((H, W, D), dtype=torch.int16, device=dev),
                  dstar=torch.empty((H, W), dtype=torch.int16, device=dev),
                  dright=torch.full((H, W), -7, dtype=torch.int16, device=dev),
-                 dsub=torch.empty((H, W), dtype=torch.float32, device=dev))
+                 dsub=torch.empty((H, W), dtype=torch.float32, device=dev),
+                 rho=torch.empty((H, W), dtype=torch.int16, device=dev),
+                 features=torch.empty((H, W, 8), dtype=torch.int16, device=dev))
         ctx.set_taps(**t)
     disp, valid = ctx.run(left, right, lid_q)
     torch.cuda.synchronize()
@@ -63,6 +65,8 @@ def run_gpu(frame, pkw, taps=True):
         out["dstar"] = t["dstar"].cpu().numpy()
         out["dright"] = t["dright"].cpu().numpy()
         out["dsub"] = t["dsub"].cpu().numpy()
+        out["rho"] = t["rho"].cpu().numpy().view(np.uint16)
+        out["features"] = t["features"].cpu().numpy().view(np.uint16)
     ctx.close()
     return out
 
@@ -72,6 +76,11 @@ def run_oracle(frame, pkw):
     lid = oracle.quantize_lidar(frame["lidar"], op.D)
     r = oracle.run(op, frame["left"], frame["right"], lid, taps=True)
     r["lidar_q"] = lid
+    r["rho"] = oracle.lidar_residual(r["dstar"], lid, op.D, op.rc)
+    f = oracle.surrogate_features(r["S"], r["dstar"], r["rho"], op.num_paths, op.b * op.p2)
+    feats = np.zeros(f.shape[:2] + (8,), np.uint16)
+    feats[..., :5] = oracle.bf16_round(f)
+    r["features"] = feats
     return r
 
 
@@ -88,6 +97,9 @@ def assert_parity(g, o, pkw, taps=True):
             assert (g["dright"] == o["dright"]).all(), "d'"
         diff = np.abs(g["dsub"] - o["dsub"])
         assert diff.max() <= SUB_TOL, f"dsub max diff {diff.max()}"
+        assert (g["rho"] == o["rho"]).all(), "LiDAR residual"
+        bad = g["features"] != o["features"]
+        assert not bad.any(), f"surrogate features differ at {np.argwhere(bad)[:5]}"
     assert (g["valid"] == o["valid"]).all(), f"mask mismatch {np.argwhere(g['valid'] != o['valid'])[:5]}"
     assert (g["disp"][g["valid"] == 0] == -1.0).all()
     d = np.abs(g["disp"] - o["disp"])

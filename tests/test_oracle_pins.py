@@ -448,3 +448,52 @@ def test_tab2_defaults():
     assert (P.ts, P.rs, P.p1, P.p2, P.q1, P.q2, P.tc, P.rc) == tuple(
         int(rows[k]) for k in ("Ts", "rs", "P1", "P2", "Q1", "Q2", "Tc", "rc"))
     assert Fraction(P.a, P.b) == Fraction(rows["alpha"])
+
+
+# ------------------------------------------------- LiDAR residual, features --
+def test_lidar_residual_matches_check_and_special_cases():
+    """rho <= Tc reproduces the LiDAR half of Eq. 6 (pinned above by brute
+    force); rc = 0 gives |d* - D-bar_p| at the pixel itself; no LiDAR gives
+    65535."""
+    rng = np.random.default_rng(21)
+    H, W, D = 40, 70, 64
+    dstar = rng.integers(0, D, size=(H, W)).astype(np.int32)
+    lid = np.where(rng.random((H, W)) < 0.03, rng.integers(0, D, size=(H, W)), -1).astype(np.int16)
+    for rc in (0, 3, 9):
+        rho = oracle.lidar_residual(dstar, lid, D, rc)
+        for tc in (0, 1, 2, 5):
+            _, valid = oracle.check(dstar, None, lid, None, tc, rc, 2)
+            assert ((rho <= tc) == (valid == 1)).all()
+    rho0 = oracle.lidar_residual(dstar, lid, D, 0)
+    has = lid >= 0
+    assert (rho0[has] == np.abs(dstar[has] - lid[has])).all()
+    assert (rho0[~has] == 65535).all()
+    assert (oracle.lidar_residual(dstar, np.full_like(lid, -1), D, 20) == 65535).all()
+
+
+def test_surrogate_features_worked_example():
+    """A parabolic cost curve S(d) = (d - 5)^2 + 100 (D = 16): d* = 5,
+    S(d*) = 100, second minimum over |d - 5| >= 2 is S(3) = S(7) = 104,
+    curvature S(4) - 2 S(5) + S(6) = 2."""
+    D = 16
+    S = np.array([[[(d - 5) ** 2 + 100 for d in range(D)]]], np.int32)
+    dstar = np.array([[5]], np.int32)
+    rho = np.array([[7]], np.uint16)
+    f = oracle.surrogate_features(S, dstar, rho, 8, 1200)
+    sS = np.float32(1) / np.float32(8 * 1200)
+    exp = [np.float32(100) * sS, np.float32(104) * sS, np.float32(2) * sS,
+           np.float32(5) * (np.float32(1) / np.float32(D)), np.float32(7) / np.float32(32)]
+    assert f[0, 0].tolist() == [float(v) for v in exp]
+    # range ends: no curvature; residual clipped at 32
+    dstar = np.array([[0]], np.int32)
+    f = oracle.surrogate_features(S, dstar, np.array([[65535]], np.uint16), 8, 1200)
+    assert f[0, 0, 2] == 0.0 and f[0, 0, 4] == 1.0
+    assert f[0, 0, 1] == np.float32(min((d - 5) ** 2 + 100 for d in range(2, D))) * sS
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.00390625, 1.005859375, -2.5, 3.0e-5], np.float32)
+    b = oracle.bf16_round(x)
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1.0); 1 + 1.5 * 2^-8
+    # rounds up to 1 + 2^-7
+    assert oracle.bf16_to_f32(b).tolist()[:4] == [1.0, 1.0, 1.0078125, -2.5]
