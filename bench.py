@@ -44,6 +44,25 @@ def sgm_ops_per_launch(frames: int, views: int):
     return ops16, ops32
 
 
+HBM_PEAK = 8.0e12
+
+
+def sgm_traffic(frames: int):
+    """HBM bytes per SGM launch from the committed counter summary, if it
+    was taken on the current kernel source and the same launch size."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sgm_dir_kernel_traffic.json")
+    src = os.path.join(ROOT, "paper_2504_05148_amd", "csrc", "k_sgm.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha or rec.get("frames_per_launch") != frames:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(n_frames: int):
     import oracle
     from paper_2504_05148_amd import synth
@@ -64,10 +83,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=8, help="frames per step")
+    ap.add_argument("--batch", type=int, default=16, help="frames per step")
     ap.add_argument("--latency-runs", type=int, default=200)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (reference "
                          "for HBM byte counters)")
@@ -139,30 +159,78 @@ def main():
     floor_s = ops16 / PEAK_OPS16 + ops32 / PEAK_OPS32
     peak = (ops16 + ops32) / floor_s
     achieved = (ops16 + ops32) / avg_launch_s
+    traffic = sgm_traffic(B)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
-                    unit="Tops/s", frac=round(achieved / peak, 4), traffic=None,
+                    unit="Tops/s", frac=round(achieved / peak, 4), traffic=traffic,
                     kernel="sgm_dir_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
                     ops_per_launch=int(ops16 + ops32))
+    if traffic:
+        bw = traffic / avg_launch_s
+        roofline.update(hbm_tb_s=round(bw / 1e12, 3), hbm_frac=round(bw / HBM_PEAK, 4))
     stage_ms = {k: round(v[0] / (K * B), 4) for k, v in stages.items()}
+    stream = torch.cuda.current_stream()
 
     # latency mode: one frame at a time on an idle GPU
-    p1 = sldf.default_params(batch=1)
-    ctx1 = sldf.Context(p1)
-    d1, v1 = ctx1.new_outputs()
-    lq1 = torch.empty((H, W), dtype=torch.int16, device="cuda")
-    lats = []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for i in range(args.latency_runs + 5 if args.latency_runs > 0 else 0):
-        j = i % B
-        ev0.record(stream)
-        sldf.quantize_lidar(lid_f[j], D, out=lq1)
-        ctx1.run(left[j], right[j], lq1, d1, v1)
-        ev1.record(stream)
-        ev1.synchronize()
-        if i >= 5:
-            lats.append(ev0.elapsed_time(ev1))
-    lats = np.array(lats) if lats else np.zeros(1)
-    print(f"[bench] latency p50 {np.percentile(lats, 50):.3f} ms", file=sys.stderr, flush=True)
+    lq1 = torch.empty((H, W), dtype=torch.int16, device="cuda")
+
+    def latency(ctx1):
+        d1, v1 = ctx1.new_outputs()
+        lats = []
+        for i in range(args.latency_runs + 5 if args.latency_runs > 0 else 0):
+            j = i % B
+            ev0.record(stream)
+            sldf.quantize_lidar(lid_f[j], D, out=lq1)
+            ctx1.run(left[j], right[j], lq1, d1, v1)
+            ev1.record(stream)
+            ev1.synchronize()
+            if i >= 5:
+                lats.append(ev0.elapsed_time(ev1))
+        lats = np.array(lats) if lats else np.zeros(1)
+        return dict(p50=round(float(np.percentile(lats, 50)), 4),
+                    p99=round(float(np.percentile(lats, 99)), 4), runs=int(lats.size))
+
+    lat_plain = latency(sldf.Context(sldf.default_params(batch=1)))
+    print(f"[bench] plain latency {lat_plain}", file=sys.stderr, flush=True)
+
+    # learned check: same frames, right-view pass skipped unless a frame falls back
+    learned = None
+    wpath = os.path.join(ROOT, "paper_2504_05148_amd", "weights", "surrogate_kitti.npz")
+    if os.path.exists(wpath) and not args.no_learned:
+        from paper_2504_05148_amd.train_surrogate import load_weights
+        sw, sb, meta = load_weights(wpath)
+        ctx_l = sldf.Context(sldf.default_params(batch=B, check_impl=1))
+        ctx_l.set_surrogate(sw, sb)
+        disp_l, valid_l = ctx_l.new_outputs(B)
+
+        def step_l():
+            sldf.quantize_lidar(lid_f.view(B * H, W), D, out=lid_q.view(B * H, W))
+            ctx_l.run_batch(left, right, lid_q, disp_l, valid_l)
+
+        for _ in range(args.warmup):
+            step_l()
+        torch.cuda.synchronize()
+        ctx_l.timing_enable(K)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            step_l()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st_l = ctx_l.timing_read()
+        ctx_l.timing_enable(0)
+        counts, limit = ctx_l.fallback_read(B)
+        agree = float((valid_l == valid).float().mean().item())
+        c1 = sldf.Context(sldf.default_params(batch=1, check_impl=1))
+        c1.set_surrogate(sw, sb)
+        learned = dict(value=round(K * B / el, 2), unit="frames/s",
+                       speedup=round((K * B / el) / fps, 4), mask_agreement=round(agree, 6),
+                       fallback_frames=int(sum(c > limit for c in counts)), frames=B,
+                       latency_ms=latency(c1),
+                       stage_ms_per_frame={k: round(v[0] / (K * B), 4) for k, v in st_l.items()},
+                       heldout_agreement=meta.get("eval", {}).get("no_fallback", {}).get(
+                           "agreement"))
+        print(f"[bench] learned {learned['value']} frames/s, agreement {agree:.5f}",
+              file=sys.stderr, flush=True)
 
     out = dict(metric=METRIC, value=round(fps, 2), unit="frames/s", n_gpus=1, steps=K,
                warmup=args.warmup, ms_per_step=round(elapsed / K * 1e3, 4),
@@ -172,10 +240,8 @@ def main():
                                     "stereo-LiDAR check (Tab. II), plain check",
                            frames_per_step=B, width=W, height=H, max_disp=D,
                            check="plain", parallelism="single GPU, batched frames"),
-               latency_ms=dict(p50=round(float(np.percentile(lats, 50)), 4),
-                               p99=round(float(np.percentile(lats, 99)), 4),
-                               runs=int(lats.size)),
-               stage_ms_per_frame=stage_ms, roofline=roofline, learned_check=None)
+               latency_ms=lat_plain,
+               stage_ms_per_frame=stage_ms, roofline=roofline, learned_check=learned)
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
     print(json.dumps(out), flush=True)

@@ -222,7 +222,8 @@ sldf_status sldf_timing_read(sldf_ctx* ctx, double* ms, int64_t* launches);
 
 /* ---- Learned consistency check (an extension beside the paper's method;
    the plain check of Eq. 6 stays the reference and the fallback) ----
-   Network: 3x3 convolutions with dilations 1, 2, 4, 8; channels
+   Network: 3x3 convolutions with dilations 1, 3, 9, 27 (an 81 x 81 receptive
+   field covered without gaps); channels
    5 (+3 zero) -> 32 -> 32 -> 32 -> 1; ReLU after the first three; bf16
    weights and activations, fp32 accumulation; logit > 0 means "consistent".
    Parameter blob (device, caller-owned, may be shared by contexts):
@@ -238,6 +239,13 @@ int32_t sldf_surrogate_num_biases(void);
    kept, not copied; NULL detaches).  Errors: EINVAL. */
 sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
                                        const float* biases);
+
+/* Monitoring (host-synchronous: call after the stream of the last run has
+   completed): copies the per-frame count of uncertain pixels of the last
+   learned-check run into counts[n] (host) and the fallback limit
+   (tau * W * H) into *limit; frame f fell back iff counts[f] > *limit.
+   Errors: EINVAL, ESTATE (context without the learned check), EDEVICE. */
+sldf_status sldf_fallback_read(sldf_ctx* ctx, int32_t* counts, int32_t n, int32_t* limit);
 
 /* Forward pass on given inputs (device): x0 bf16 [F][H][W][8] (the
    `features` tap layout) -> logits float [F][H][W]; act1..act3 bf16

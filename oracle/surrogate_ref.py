@@ -3,7 +3,7 @@ CPU.  Test infrastructure only (like the rest of this package): the HIP
 kernels are checked against it, never the other way round.
 
 The network is the one the library runs for check_impl = 1: four 3x3
-convolutions with dilations 1, 2, 4, 8 and channels 8 (5 used) -> 32 -> 32
+convolutions with dilations 1, 3, 9, 27 and channels 8 (5 used) -> 32 -> 32
 -> 32 -> 1, ReLU after the first three.  Inputs and weights are bf16 values;
 accumulation is fp32; the stored hidden activations are rounded to bf16 (round
 to nearest even), as the kernels store them.
@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 # packed weight layout per layer: [9 taps][out][in], taps in raster order
-LAYERS = [(32, 8, 1), (32, 32, 2), (32, 32, 4), (16, 32, 8)]   # (out_pad, in, dilation)
+LAYERS = [(32, 8, 1), (32, 32, 3), (32, 32, 9), (16, 32, 27)]   # (out_pad, in, dilation)
 COUT = [32, 32, 32, 1]
 N_W = sum(9 * o * i for o, i, _ in LAYERS)
 N_B = 32 + 32 + 32 + 1

@@ -1,5 +1,5 @@
 // Learned consistency surrogate: a 4-layer 3x3 CNN (5 -> 32 -> 32 -> 32 -> 1
-// channels, dilations 1, 2, 4, 8, ReLU between layers) that predicts the
+// channels, dilations 1, 3, 9, 27, ReLU between layers) that predicts the
 // validity mask of the stereo-LiDAR check (Eq. 6) from left-view cost
 // features, so that the right-view SGM pass can be skipped.  BF16 weights and
 // activations, FP32 accumulation on the matrix cores

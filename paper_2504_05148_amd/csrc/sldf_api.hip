@@ -595,6 +595,16 @@ sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
     return SLDF_OK;
 }
 
+sldf_status sldf_fallback_read(sldf_ctx* ctx, int32_t* counts, int32_t n, int32_t* limit)
+{
+    if (!ctx || !counts || !limit || n < 1 || n > ctx->p.batch) return SLDF_EINVAL;
+    if (ctx->p.check_impl != 1) return SLDF_ESTATE;
+    if (hipMemcpy(counts, ctx->buf.counter, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return SLDF_EDEVICE;
+    *limit = (int32_t)(ctx->p.fallback_tau * (float)ctx->p.width * (float)ctx->p.height);
+    return SLDF_OK;
+}
+
 namespace {
 
 hipError_t surrogate_forward(const uint16_t* x0, int W, int H, int F, const uint16_t* w,

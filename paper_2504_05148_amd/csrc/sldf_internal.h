@@ -130,7 +130,9 @@ constexpr int kSurOffW1 = 0, kSurOffW2 = kSurW1, kSurOffW3 = kSurOffW2 + kSurW2,
               kSurOffW4 = kSurOffW3 + kSurW3, kSurNW = kSurOffW4 + kSurW4;
 constexpr int kSurNB = 32 + 32 + 32 + 1;
 constexpr int kSurOffB1 = 0, kSurOffB2 = 32, kSurOffB3 = 64, kSurOffB4 = 96;
-constexpr int kSurDil[4] = {1, 2, 4, 8};
+// dilations 1, 3, 9, 27: the composite offsets sum_l k_l 3^l (k_l in -1..1)
+// cover every offset in [-40, 40] exactly once (an 81 x 81 receptive field)
+constexpr int kSurDil[4] = {1, 3, 9, 27};
 
 struct ConvArgs {
     const uint16_t* x;        // NHWC bf16 input [F][H][W][cin]

@@ -75,6 +75,8 @@ def lib():
         L.sldf_timing_enable.argtypes = [_vp, _i32]
         L.sldf_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+        L.sldf_fallback_read.argtypes = [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]
+        L.sldf_fallback_read.restype = ctypes.c_int
         L.sldf_surrogate_num_weights.restype = _i32
         L.sldf_surrogate_num_biases.restype = _i32
         L.sldf_surrogate_set_weights.argtypes = [_vp, _vp, _vp]
@@ -222,6 +224,15 @@ class Context:
         _check(lib().sldf_surrogate_set_weights(
             self._h, _ptr(weights) if weights is not None else None,
             _ptr(biases) if biases is not None else None), "sldf_surrogate_set_weights")
+
+    def fallback_read(self, n: int):
+        """(per-frame uncertain-pixel counts of the last learned run, limit);
+        synchronises with the device."""
+        counts = (_i32 * n)()
+        lim = _i32()
+        _check(lib().sldf_fallback_read(self._h, counts, n, ctypes.byref(lim)),
+               "sldf_fallback_read")
+        return list(counts), int(lim.value)
 
     def timing_read(self):
         """{stage: (total_ms, launches)} since the last read (waits on events)."""

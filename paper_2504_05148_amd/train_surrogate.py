@@ -1,0 +1,204 @@
+"""Train the learned consistency check on seeded synthetic paper-scale frames.
+
+Labels are the masks of the plain stereo-LiDAR check (Eq. 6) computed by the
+library on the same frames; inputs are the library's surrogate features.
+Training runs entirely through the C ABI (MFMA forward / backward, Adam on
+fp32 master weights).  Frames 0..n_train-1 of the surrogate workload train,
+the next n_heldout evaluate: mask agreement with the plain check (fallback
+off and on), and the 3-px error rate of both outputs against the synthetic
+ground truth.
+
+  python -m paper_2504_05148_amd.train_surrogate --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "weights", "surrogate_kitti.npz")
+
+
+def _gen(idx):
+    from paper_2504_05148_amd import synth
+    f = synth.make_frame(synth.KITTI, synth.CONFIG_IDS["surrogate"], idx)
+    return idx, f["left"], f["right"], f["lidar"], f["gt"], f["occ"]
+
+
+def _log(msg):
+    print(f"[train] {msg}", flush=True)
+
+
+def load_weights(path=DEFAULT_OUT, device="cuda"):
+    """(weights int16 bf16-bits tensor, biases float32 tensor, metadata)."""
+    import torch
+    z = np.load(path, allow_pickle=False)
+    w = torch.from_numpy(z["weight_bits"].view(np.int16).copy()).to(device)
+    b = torch.from_numpy(z["biases"].astype(np.float32)).to(device)
+    meta = json.loads(str(z["meta"])) if "meta" in z else {}
+    return w, b, meta
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--heldout", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--workers", type=int, default=14)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    args = ap.parse_args(argv)
+
+    import torch
+    from paper_2504_05148_amd import sldf
+
+    torch.cuda.set_device(0)
+    W, H, D = 1242, 375, 128
+    N = args.train + args.heldout
+    p = sldf.default_params()
+    ctx = sldf.Context(p)
+    x0 = torch.empty((N, H, W, 8), dtype=torch.int16, device="cuda")
+    rho = torch.empty((N, H, W), dtype=torch.int16, device="cuda")
+    lab = torch.empty((N, H, W), dtype=torch.uint8, device="cuda")
+    disp_plain = torch.empty((args.heldout, H, W), dtype=torch.float32, device="cuda")
+    gts, occs, inputs = {}, {}, {}
+    t0 = time.time()
+    with Pool(args.workers) as pool:
+        for k, (idx, left, right, lid, gt, occ) in enumerate(
+                pool.imap_unordered(_gen, range(N), chunksize=4)):
+            L, R = sldf.device_image(left), sldf.device_image(right)
+            lq = sldf.quantize_lidar(torch.from_numpy(lid).cuda(), D)
+            ctx.set_taps(features=x0[idx], rho=rho[idx])
+            d, v = ctx.run(L, R, lq)
+            lab[idx].copy_(v)
+            if idx >= args.train:
+                j = idx - args.train
+                disp_plain[j].copy_(d)
+                gts[j], occs[j] = gt, occ
+                inputs[j] = (L, R, lq)
+            if (k + 1) % 200 == 0:
+                torch.cuda.synchronize()
+                _log(f"labelled {k + 1}/{N} frames ({time.time() - t0:.0f} s)")
+    ctx.set_taps()
+    torch.cuda.synchronize()
+    _log(f"labels: valid fraction {lab[:args.train].float().mean().item():.4f}")
+
+    # He-uniform init (padding zero), fp32 master
+    rng = np.random.default_rng(args.seed)
+    nw, nb = sldf.surrogate_sizes()
+    master = np.zeros(nw + nb, np.float32)
+    off = 0
+    for (oc, ic), cout, cin_used in zip([(32, 8), (32, 32), (32, 32), (16, 32)],
+                                        [32, 32, 32, 1], [5, 32, 32, 32]):
+        blk = np.zeros((9, oc, ic), np.float32)
+        bound = np.sqrt(6.0 / (9 * cin_used))
+        blk[:, :cout, :cin_used] = rng.uniform(-bound, bound, size=(9, cout, cin_used))
+        master[off:off + blk.size] = blk.ravel()
+        off += blk.size
+    master[-1] = 3.0      # start from "consistent" (most pixels are)
+    tr = sldf.SurrogateTrainer(W, H, args.batch, torch.from_numpy(master), lr=args.lr)
+
+    steps_per_epoch = args.train // args.batch
+    total = steps_per_epoch * args.epochs
+    step = 0
+    g = torch.Generator().manual_seed(args.seed)
+    for ep in range(args.epochs):
+        perm = torch.randperm(args.train, generator=g)
+        acc_l, acc_a, acc_n = 0.0, 0.0, 0.0
+        for s in range(steps_per_epoch):
+            idx = perm[s * args.batch:(s + 1) * args.batch].cuda()
+            # cosine learning-rate decay
+            tr.lr = args.lr * 0.5 * (1 + np.cos(np.pi * step / total))
+            st = tr.step(x0[idx].contiguous(), lab[idx].contiguous(), rho[idx].contiguous(),
+                         p.tc)
+            stats = st.cpu().numpy()
+            acc_l += stats[0]
+            acc_a += stats[2]
+            acc_n += args.batch * W * H
+            step += 1
+        _log(f"epoch {ep + 1}/{args.epochs}: loss {acc_l / steps_per_epoch:.4f} "
+             f"train agreement {acc_a / acc_n:.4f} ({time.time() - t0:.0f} s)")
+
+    # fallback trade-off on the held-out frames: per frame, the number of
+    # LiDAR-undecided pixels with |logit| < margin, and the agreement of the
+    # learned mask without fallback; a frame falls back when its count
+    # exceeds tau * W * H, and then agrees exactly.
+    Hn = args.heldout
+    z, _ = sldf.surrogate_forward(x0[args.train:], tr.weights, tr.biases)
+    undecided = (rho[args.train:].to(torch.int32) & 0xFFFF) > p.tc   # uint16 bits
+    lab_h = lab[args.train:].bool()
+    learned = (z > 0) | ~undecided
+    agree_f = (learned == lab_h).flatten(1).float().mean(1).cpu().numpy()
+    sweep = []
+    for margin in (0.25, 0.5, 1.0, 2.0):
+        unc = ((z.abs() < margin) & undecided).flatten(1).sum(1).cpu().numpy() / (W * H)
+        order = np.sort(unc)
+        for q in np.linspace(0.0, 1.0, 21):
+            tau = float(order[min(int(q * (Hn - 1)), Hn - 1)]) if q < 1 else 1.0
+            fb = unc > tau
+            agree = float(np.where(fb, 1.0, agree_f).mean())
+            sweep.append(dict(margin=margin, tau=tau, fallback_rate=float(fb.mean()),
+                              agreement=agree))
+    ok = [r for r in sweep if r["agreement"] >= 0.99]
+    best = min(ok, key=lambda r: (r["fallback_rate"], -r["agreement"])) if ok else None
+    _log(f"held-out agreement without fallback {agree_f.mean():.5f}; "
+         f"cheapest setting reaching 0.99: {best}")
+
+    # held-out evaluation through the learned sldf_run
+    res = {}
+    settings = [("no_fallback", 1.0, 0.0), ("default_fallback", p.fallback_tau,
+                                             p.uncertain_margin)]
+    if best is not None:
+        settings.append(("tuned_fallback", best["tau"], best["margin"]))
+    for name, tau, margin in settings:
+        pl = sldf.default_params(check_impl=1, fallback_tau=tau, uncertain_margin=margin)
+        cl = sldf.Context(pl)
+        cl.set_surrogate(tr.weights, tr.biases)
+        agree, n, err_l, err_p, cov_l, cov_p = 0, 0, 0, 0, 0, 0
+        for j in range(args.heldout):
+            L, R, lq = inputs[j]
+            d, v = cl.run(L, R, lq)
+            vp = lab[args.train + j]
+            agree += int((v == vp).sum().item())
+            n += W * H
+            gt = torch.from_numpy(gts[j]).cuda()
+            noc = torch.from_numpy(~occs[j]).cuda()
+            for disp, acc in ((d, "l"), (disp_plain[j], "p")):
+                m = (disp >= 0) & noc
+                e = int(((disp - gt).abs()[m] >= 3).sum().item())
+                c = int(m.sum().item())
+                if acc == "l":
+                    err_l += e
+                    cov_l += c
+                else:
+                    err_p += e
+                    cov_p += c
+        res[name] = dict(tau=tau, margin=margin,
+                         agreement=agree / n, covered_error_learned=err_l / max(cov_l, 1),
+                         covered_error_plain=err_p / max(cov_p, 1),
+                         coverage_learned=cov_l / (args.heldout * W * H),
+                         coverage_plain=cov_p / (args.heldout * W * H))
+        _log(f"held-out {name}: {res[name]}")
+
+    meta = dict(train_frames=args.train, heldout_frames=args.heldout, epochs=args.epochs,
+                batch=args.batch, lr=args.lr, seed=args.seed, workload="1242x375 D=128 "
+                "synthetic paper-scale frames (config id 4)", eval=res,
+                fallback_sweep=sweep, tuned=best)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.savez(args.out, master=tr.master.cpu().numpy(),
+             weight_bits=tr.weights.cpu().numpy().view(np.uint16),
+             biases=tr.biases.cpu().numpy(), meta=json.dumps(meta))
+    _log(f"saved {args.out}")
+    print(json.dumps(meta), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -74,7 +74,7 @@ def test_workspace_size_plan():
     ("rs", 16, sldf.EINVAL),
     ("rc", 32, sldf.EINVAL),
     ("check_mode", 4, sldf.EINVAL),
-    ("check_impl", 1, sldf.EINVAL),
+    ("check_impl", 2, sldf.EINVAL),
     ("batch", 0, sldf.EINVAL),
     ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
 ])
@@ -83,6 +83,22 @@ def test_validation(field, value, status):
     with pytest.raises(sldf.SldfError) as ei:
         sldf.workspace_size(p)
     assert ei.value.status == status
+
+
+def test_learned_check_needs_full_check_mode():
+    for mode in (0, 1, 2):
+        with pytest.raises(sldf.SldfError) as ei:
+            sldf.workspace_size(sldf.default_params(check_impl=1, check_mode=mode))
+        assert ei.value.status == sldf.EINVAL
+    with pytest.raises(sldf.SldfError):
+        sldf.workspace_size(sldf.default_params(check_impl=1, fallback_tau=1.5))
+    # learned check adds activations, logits and counters to the workspace
+    assert sldf.workspace_size(sldf.default_params(check_impl=1)) > \
+        sldf.workspace_size(sldf.default_params()) + 2 * 1242 * 375 * 64
+
+
+def test_surrogate_sizes():
+    assert sldf.surrogate_sizes() == (25344, 97)
 
 
 def test_overflow_bound_is_tight():

@@ -206,10 +206,10 @@ def test_batch_matches_single_frames():
 
 
 def test_paper_scale_batch_launch_configuration():
-    """The benchmark's launch configuration (8 frames per batch call) at
+    """The benchmark's launch configuration (16 frames per batch call) at
     1242 x 375, D = 128: first and last frame against the oracle, the others
     against single-frame runs."""
-    B = 8
+    B = 16
     frames = [synth.kitti_frame(i) for i in range(B)]
     p = sldf.default_params(batch=B)
     ctx = sldf.Context(p)
