@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (reference "
                          "for HBM byte counters)")
@@ -242,6 +243,25 @@ def main():
                            check="plain", parallelism="single GPU, batched frames"),
                latency_ms=lat_plain,
                stage_ms_per_frame=stage_ms, roofline=roofline, learned_check=learned)
+    if args.serving_seconds > 0:
+        # serving: six rigs (640x480 D=64, 1242x375 D=128, 1920x1080 D=256),
+        # Poisson arrivals at 300 frames/s in total, continuous batching
+        from paper_2504_05148_amd import serving
+        pools = serving.make_pools(6, 8)
+        srv = {}
+        for ci in (0, 1):
+            sur = None
+            if ci:
+                from paper_2504_05148_amd.train_surrogate import load_weights
+                sur = load_weights(wpath)[:2]
+            s_, _, _ = serving.run_serving(args.serving_seconds, pool_size=8, check_impl=ci,
+                                           surrogate=sur, pools=pools)
+            srv[s_["check"]] = {k: s_[k] for k in ("requests", "completed", "failed",
+                                                  "frames_per_s", "offered_frames_per_s",
+                                                  "p50_ms", "p99_ms", "batches")}
+            print(f"[bench] serving {s_['check']}: {srv[s_['check']]}", file=sys.stderr,
+                  flush=True)
+        out["serving"] = srv
     if not args.no_cpu_baseline and args.cpu_frames > 0:
         out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
     print(json.dumps(out), flush=True)

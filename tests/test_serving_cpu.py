@@ -1,0 +1,66 @@
+"""Serving scheduler on the CPU with a fake backend: admission by HBM budget,
+continuous batching, failure handling, latency accounting."""
+from paper_2504_05148_amd.serving import FakeBackend, Server, poisson_arrivals, summarize
+
+
+def test_budget_bounds_slots_and_everything_completes():
+    be = FakeBackend(cost=[0.002, 0.004], slot_bytes=[10, 30])
+    srv = Server(be, 2, hbm_budget=50, max_batch=4)
+    arr = poisson_arrivals([400.0, 300.0], 0.3, pool_size=4, seed=1)
+    fin = srv.run(arr, realtime=True)
+    assert len(fin) == len(arr) and not srv.failed
+    assert srv.peak_bytes <= 50
+    assert all(r.done >= r.start >= r.arrival for r in fin)
+
+
+def test_continuous_batching_under_load():
+    # one slot, one stream: requests arriving during a launch join the next one
+    be = FakeBackend(cost=[0.01], slot_bytes=[1])
+    srv = Server(be, 1, hbm_budget=1, max_batch=4, n_streams=1)
+    arr = [(0.001 * i, 0, i % 3) for i in range(40)]
+    fin = srv.run(arr, realtime=True)
+    assert len(fin) == 40
+    assert max(srv.batches) == 4 and sum(k * v for k, v in srv.batches.items()) == 40
+    # every launch after the first takes what queued while the previous ran
+    assert srv.batches[4] >= 8
+
+
+def test_budget_too_small_for_a_rig_never_allocates():
+    be = FakeBackend(cost=[0.001, 0.001], slot_bytes=[10, 100])
+    srv = Server(be, 2, hbm_budget=50, max_batch=2)
+    arr = [(0.0, 0, 0), (0.0, 1, 0), (0.001, 0, 1)]
+    done = {}
+
+    def prog(a, b):
+        pass
+    # rig 1 can never get a slot: stop after a short while by running rig 0 only
+    fin = srv.run([a for a in arr if a[1] == 0], realtime=True, progress=prog)
+    assert len(fin) == 2 and srv.peak_bytes == 10
+    assert srv._get_slot(1) is None
+
+
+def test_failed_launches_release_resources():
+    be = FakeBackend(cost=[0.001, 0.001], slot_bytes=[1, 1], fail_rigs=[1])
+    srv = Server(be, 2, hbm_budget=10, max_batch=2)
+    arr = poisson_arrivals([500.0, 500.0], 0.05, pool_size=2, seed=3)
+    fin = srv.run(arr, realtime=True)
+    n1 = sum(1 for a in arr if a[1] == 1)
+    assert len(srv.failed) == n1 and all(r.rig == 1 for r in srv.failed)
+    assert len(fin) == len(arr) - n1
+    s = summarize(fin, srv.failed, 0.05, 2)
+    assert s["failed"] == n1 and s["completed"] == len(fin)
+
+
+def test_oldest_request_first_across_rigs():
+    be = FakeBackend(cost=[0.005, 0.005, 0.005], slot_bytes=[1, 1, 1])
+    srv = Server(be, 3, hbm_budget=3, max_batch=1, n_streams=1)
+    arr = [(0.0, 2, 0), (0.0001, 0, 0), (0.0002, 1, 0)]
+    fin = srv.run(arr, realtime=True)
+    order = [r.rig for r in sorted(fin, key=lambda r: r.start)]
+    assert order == [2, 0, 1]
+
+
+def test_poisson_arrivals_rates():
+    arr = poisson_arrivals([50.0] * 6, 20.0, pool_size=16)
+    assert 5600 < len(arr) < 6400
+    assert all(arr[i][0] <= arr[i + 1][0] for i in range(len(arr) - 1))
