@@ -32,30 +32,39 @@ PEAK_OPS32 = 256 * 64 * 2.4e9
 PEAK_OPS16 = 2 * PEAK_OPS32
 
 
-def sgm_ops_per_launch(frames: int, views: int):
-    """Algorithmic integer ops of one SGM path pass (one direction, both
-    views, all frames).  Per cell (pixel x disparity): the Eq. 2 step is 9
+def sgm_ops_per_launch(frames: int, views: int, directions: int = 2):
+    """Algorithmic integer ops of one SGM launch: `directions` path
+    directions (a launch runs a direction and its opposite), both views, all
+    frames.  Per cell (pixel x disparity) and direction: the Eq. 2 step is 9
     ops (two +P1, three mins, -m, +C, running min, +S) on 16-bit data; the
     joint cost is xor + popcount (32-bit) plus the (1-alpha) scaling and, in
-    the left view, the DDC add (16-bit)."""
+    the left view, the DDC add (16-bit).  Work the kernel adds on top of the
+    method (the recomputed forward states of the pair scheme) is not
+    counted."""
     cells = frames * W * H * D
-    ops32 = 2 * cells * views
-    ops16 = cells * (9 + 2) + (views - 1) * cells * (9 + 1)
+    ops32 = 2 * cells * views * directions
+    ops16 = (cells * (9 + 2) + (views - 1) * cells * (9 + 1)) * directions
     return ops16, ops32
 
 
 HBM_PEAK = 8.0e12
+# sources of the SGM pair kernel: a counter summary taken on other sources
+# no longer describes it
+SGM_SOURCES = ("k_sgm_pair.hip", "sgm_common.h", "sldf_internal.h")
 
 
 def sgm_traffic(frames: int):
     """HBM bytes per SGM launch from the committed counter summary, if it
     was taken on the current kernel source and the same launch size."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sgm_dir_kernel_traffic.json")
-    src = os.path.join(ROOT, "paper_2504_05148_amd", "csrc", "k_sgm.hip")
+    path = os.path.join(ROOT, "profiles", "sgm_pair_kernel_traffic.json")
+    csrc = os.path.join(ROOT, "paper_2504_05148_amd", "csrc")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for name in SGM_SOURCES:
+            h.update(open(os.path.join(csrc, name), "rb").read())
+        sha = h.hexdigest()
     except OSError:
         return None
     if rec.get("source_sha256") != sha or rec.get("frames_per_launch") != frames:
@@ -163,7 +172,7 @@ def main():
     traffic = sgm_traffic(B)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
                     unit="Tops/s", frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="sgm_dir_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
+                    kernel="sgm_pair_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
                     ops_per_launch=int(ops16 + ops32))
     if traffic:
         bw = traffic / avg_launch_s

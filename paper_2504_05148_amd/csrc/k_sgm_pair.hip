@@ -1,0 +1,217 @@
+// SGM path aggregation for a pair of opposite directions r and -r in one
+// launch (Sec. III, Eq. 2), with the joint cost fused in (Eq. 4) and, for
+// the last pair, the winner-takes-all + subpixel step (Eq. 3).
+//
+// Opposite directions walk the same lines in opposite orders.  For each line
+// (owned by G = D / 8 lanes, see sgm_common.h):
+//   1. the forward direction r runs over the whole line and stores its
+//      state L_r every kSeg pixels (a checkpoint per segment, 1 / kSeg of
+//      the cost volume) in a scratch buffer;
+//   2. the segments are then visited from the last to the first: the
+//      forward states of the segment are recomputed from the checkpoint into
+//      registers (with the joint costs of its pixels), and the backward
+//      direction -r, whose state runs on continuously, walks the segment in
+//      reverse and adds L_r + L_-r into S (or takes the WTA).
+// S is therefore read and written once per pair instead of once per
+// direction; the price is one extra forward recurrence per pixel (the
+// costs are computed twice, as in two separate passes).
+#include "sgm_common.h"
+
+namespace sldf {
+
+constexpr int kSeg = 4;   // checkpoint interval (pixels per segment)
+
+template <int G, int MODE, int VIEW>
+__device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, int line,
+                                         int g, int frame, int fv)
+{
+    constexpr int D = G * 8;
+    constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
+    constexpr bool kStoreS = MODE == kFirst || MODE == kMiddle;
+    int x0, y0, len;
+    line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
+    const int d0 = g * 8;
+    const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
+    const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
+    const int16_t* __restrict__ prior =
+        VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
+    uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
+    uint32_t* __restrict__ ck =
+        a.ckpt + (((size_t)fv * a.nlines + line) * a.ckpt_segs * G + g) * 4;
+    const uint32_t p1x2 = a.p1s * 0x10001u;
+    const bool gfirst = g == 0, glast = g == G - 1;
+    const uint32_t dc = (uint32_t)(a.dy * a.census_pitch + a.dx);
+    const uint32_t dp = (uint32_t)(a.dy * a.prior_pitch + a.dx);
+    const uint32_t dpx = (uint32_t)(a.dy * a.W + a.dx);
+    const PixOff o0{(uint32_t)(y0 * a.census_pitch + x0 + D), (uint32_t)(y0 * a.prior_pitch + x0),
+                    (uint32_t)(y0 * a.W + x0)};
+    auto pix = [&](int t) {
+        return PixOff{o0.oc + (uint32_t)t * dc, o0.op + (uint32_t)t * dp,
+                      o0.opx + (uint32_t)t * dpx};
+    };
+    auto load = [&](StepIn& b, int t) { load_pixel<D, VIEW>(cbase, cmatch, prior, pix(t), d0, b); };
+
+    // ---- 1. forward direction over the whole line, checkpoints ----
+    {
+        uint32_t L[4] = {0, 0, 0, 0};
+        uint32_t m = 0;
+        auto fstep = [&](const StepIn& in, int t) {
+            uint32_t C[4];
+            cost8<D, VIEW>(a, pat, in, x0 + t * a.dx, d0, C);
+            rec8<G>(L, m, C, t == 0, p1x2, a.p2s, gfirst, glast);
+            if ((t + 1) % kSeg == 0 && t + 1 < len)
+                *reinterpret_cast<u32x4*>(ck + (size_t)((t + 1) / kSeg - 1) * G * 4) =
+                    u32x4{L[0], L[1], L[2], L[3]};
+        };
+        StepIn b0, b1, b2;
+        load(b0, 0);
+        if (len > 1) load(b1, 1);
+        if (len > 2) load(b2, 2);
+        for (int t = 0; t < len; t += 3) {
+            fstep(b0, t);
+            if (t + 3 < len) load(b0, t + 3);
+            if (t + 1 >= len) break;
+            fstep(b1, t + 1);
+            if (t + 4 < len) load(b1, t + 4);
+            if (t + 2 >= len) break;
+            fstep(b2, t + 2);
+            if (t + 5 < len) load(b2, t + 5);
+        }
+    }
+
+    // ---- 2. segments from the end: recompute forward, walk backward ----
+    // Software pipeline: while segment s is walked backward, the census and
+    // checkpoint of segment s - 1 are already in flight, and each S slot is
+    // refilled with the S of segment s - 1 as soon as it has been consumed.
+    // Only the last segment can be shorter than kSeg.
+    const int nseg = (len + kSeg - 1) / kSeg;
+    uint32_t Lb[4] = {0, 0, 0, 0};
+    uint32_t mb = 0;
+    StepIn R[kSeg];
+    u32x4 Sin[kSeg];
+    u32x4 cin = u32x4{0u, 0u, 0u, 0u};
+    {
+        const int t0 = (nseg - 1) * kSeg;
+        const int tl = len - t0;
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j)
+            if (j < tl) load(R[j], t0 + j);
+        if (nseg > 1) cin = *reinterpret_cast<const u32x4*>(ck + (size_t)(nseg - 2) * G * 4);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            Sin[j] = u32x4{0u, 0u, 0u, 0u};
+            if (kLoadS && j < tl) Sin[j] = load_s<D>(S, pix(t0 + j).opx, d0);
+        }
+    }
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int t0 = s * kSeg;
+        const int tl = min(kSeg, len - t0);
+        uint32_t Lf[4] = {cin.x, cin.y, cin.z, cin.w};
+        uint32_t mf = 0;
+        if (s > 0) {
+            const uint32_t mn = pk_min(pk_min(Lf[0], Lf[1]), pk_min(Lf[2], Lf[3]));
+            mf = group_min<G>(min(mn & 0xffffu, mn >> 16));
+        }
+        uint32_t Cb[kSeg][4], Lbuf[kSeg][4];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            if (j < tl) {
+                cost8<D, VIEW>(a, pat, R[j], x0 + (t0 + j) * a.dx, d0, Cb[j]);
+                rec8<G>(Lf, mf, Cb[j], s == 0 && j == 0, p1x2, a.p2s, gfirst, glast);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
+            }
+        }
+        if (s > 0) {
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) load(R[j], t0 - kSeg + j);
+            if (s > 1) cin = *reinterpret_cast<const u32x4*>(ck + (size_t)(s - 2) * G * 4);
+        }
+#pragma unroll
+        for (int j = kSeg - 1; j >= 0; --j) {
+            if (j < tl) {
+                // the backward direction starts at the last pixel of the line
+                rec8<G>(Lb, mb, Cb[j], s == nseg - 1 && j == tl - 1, p1x2, a.p2s, gfirst, glast);
+                uint32_t St[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);
+                if (kLoadS) {
+                    St[0] = pk_add(St[0], Sin[j].x); St[1] = pk_add(St[1], Sin[j].y);
+                    St[2] = pk_add(St[2], Sin[j].z); St[3] = pk_add(St[3], Sin[j].w);
+                }
+                const uint32_t opx = pix(t0 + j).opx;
+                if (kStoreS) {
+                    store_s<D>(S, opx, d0, St);
+                } else {
+                    if (a.store_sum) store_s<D>(S, opx, d0, St);
+                    wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + opx);
+                }
+            }
+            // every slot of segment s - 1 is refilled, also those a short
+            // last segment left unused
+            if (kLoadS && s > 0) Sin[j] = load_s<D>(S, pix(t0 - kSeg + j).opx, d0);
+        }
+    }
+}
+
+template <int G, int MODE>
+__global__ __launch_bounds__(256) void sgm_pair_kernel(SgmArgs a)
+{
+    constexpr int D = G * 8;
+    __shared__ uint32_t pat[2 * (D + 8) + 4];
+    build_pattern<D>(a, pat);
+    __syncthreads();
+    // XCD-aware mapping (blocks are dispatched round-robin over the XCDs):
+    // each XCD takes a contiguous range of logical blocks, i.e. the lines of
+    // one frame-view, which share its L2 copy of the census rows
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int logical = (b % kXcds) * (nb / kXcds) + b / kXcds;
+    const int fv = logical / a.blocks_per_fv;
+    if (fv >= a.n_fv) return;
+    const int view = a.view_base + fv % a.nviews, frame = fv / a.nviews;
+    if (a.gate && a.gate[frame] <= a.gate_limit) return;   // fallback not needed
+    const int g = threadIdx.x % G;
+    const int line = (logical - fv * a.blocks_per_fv) * (256 / G) + threadIdx.x / G;
+    if (line >= a.nlines) return;
+    if (view == 0)
+        run_pair<G, MODE, 0>(a, pat, line, g, frame, fv);
+    else
+        run_pair<G, MODE, 1>(a, pat, line, g, frame, fv);
+}
+
+template <int G>
+static void launch_pg(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
+{
+    switch (mode) {
+    case kFirst: hipLaunchKernelGGL((sgm_pair_kernel<G, kFirst>), grid, dim3(256), 0, s, a); break;
+    case kMiddle: hipLaunchKernelGGL((sgm_pair_kernel<G, kMiddle>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((sgm_pair_kernel<G, kLast>), grid, dim3(256), 0, s, a); break;
+    }
+}
+
+int64_t sgm_pair_ckpt_segs(int W, int H, int dx, int dy)
+{
+    const int maxlen = dy == 0 ? W : dx == 0 ? H : (W < H ? W : H);
+    return (maxlen + kSeg - 1) / kSeg;
+}
+
+hipError_t launch_sgm_pair(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
+                           hipStream_t s)
+{
+    const int G = D / 8;
+    const int lines_per_block = 256 / G;
+    SgmArgs a = a0;
+    a.blocks_per_fv = (a.nlines + lines_per_block - 1) / lines_per_block;
+    a.nviews = nviews;
+    a.n_fv = nviews * nframes;
+    a.ckpt_segs = (int32_t)sgm_pair_ckpt_segs(a.W, a.H, a.dx, a.dy);
+    const int64_t nb = (int64_t)a.blocks_per_fv * a.n_fv;
+    dim3 grid((unsigned)((nb + kXcds - 1) / kXcds * kXcds));
+    if (G == 8) launch_pg<8>(a, mode, grid, s);
+    else if (G == 16) launch_pg<16>(a, mode, grid, s);
+    else launch_pg<32>(a, mode, grid, s);
+    return hipGetLastError();
+}
+
+}  // namespace sldf

@@ -1,0 +1,303 @@
+// Building blocks of the SGM path passes (Sec. III, Eq. 2-3 with the joint
+// cost of Sec. IV-A, Eq. 4): packed 2 x u16 arithmetic, DPP group
+// reductions, line geometry, per-step loads, the fused cost, one recurrence
+// step and the winner-takes-all + parabola emit.
+//
+// A line of a path direction is owned by G = D / 8 lanes of a wavefront;
+// lane g holds disparities [8g, 8g + 8) as four packed 2 x u16 registers.
+#pragma once
+
+#include "sldf_internal.h"
+
+namespace sldf {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u16x2 v2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t u1(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
+{
+    return u1(__builtin_elementwise_min(v2(a), v2(b)));
+}
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) { return u1(v2(a) + v2(b)); }
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) { return u1(v2(a) - v2(b)); }
+__device__ __forceinline__ uint32_t pk_mad(uint32_t a, uint32_t b, uint32_t c)
+{
+    return u1(v2(a) * v2(b) + v2(c));
+}
+
+// DPP controls (GFX9 encoding)
+constexpr int kQuadXor1 = 0xB1;        // quad_perm:[1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;        // quad_perm:[2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+constexpr int kWaveShr1 = 0x138;       // lane i <- lane i-1
+constexpr int kWaveShl1 = 0x130;       // lane i <- lane i+1
+
+constexpr int kXcds = 8;               // MI355X: 8 XCDs, one L2 each
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return __builtin_amdgcn_update_dpp(0u, v, CTRL, 0xf, 0xf, true);
+}
+
+// Minimum over the G lanes of a group, broadcast to all of them.
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v)
+{
+    v = min(v, dpp<kQuadXor1>(v));
+    v = min(v, dpp<kQuadXor2>(v));
+    v = min(v, dpp<kRowHalfMirror>(v));
+    if (G >= 16) v = min(v, dpp<kRowMirror>(v));
+    if (G >= 32) {
+        auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = min(sw[0], sw[1]);
+    }
+    return v;
+}
+
+// First pixel and length of line `line` of direction (dx, dy): rows for
+// horizontal steps, columns for vertical ones, W + H - 1 diagonals otherwise
+// (first the ones starting on the top / bottom row, then the side column).
+__device__ __forceinline__ void line_start(int line, int W, int H, int dx, int dy, int& x,
+                                           int& y, int& len)
+{
+    if (dy == 0) {
+        y = line;
+        x = dx > 0 ? 0 : W - 1;
+        len = W;
+    } else if (dx == 0) {
+        x = line;
+        y = dy > 0 ? 0 : H - 1;
+        len = H;
+    } else {
+        if (line < W) {
+            x = line;
+            y = dy > 0 ? 0 : H - 1;
+        } else {
+            int k = line - W + 1;
+            x = dx > 0 ? 0 : W - 1;
+            y = dy > 0 ? k : H - 1 - k;
+        }
+        int nx = dx > 0 ? W - x : x + 1;
+        int ny = dy > 0 ? H - y : y + 1;
+        len = nx < ny ? nx : ny;
+    }
+}
+
+// Inputs of one step (one pixel of the line) for one lane.
+struct StepIn {
+    uint32_t cb;        // census of the base pixel
+    u32x4a4 m0, m1;     // census of 8 consecutive matching pixels
+    int32_t e;          // prior disparity (-1 = none)
+};
+
+// Offsets of one pixel: census (padded rows, pixel x at x + D), prior, pixel.
+struct PixOff {
+    uint32_t oc, op, opx;
+};
+
+template <int D, int VIEW>
+__device__ __forceinline__ void load_pixel(const uint32_t* __restrict__ cbase,
+                                           const uint32_t* __restrict__ cmatch,
+                                           const int16_t* __restrict__ prior, const PixOff& o,
+                                           int d0, StepIn& st)
+{
+    st.cb = cbase[o.oc];
+    // matching pixels: x - d (left base, descending) or x + d (right base)
+    // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
+    const uint32_t om = VIEW == 0 ? o.oc - (uint32_t)(d0 + 7) : o.oc + (uint32_t)d0;
+    st.m0 = *reinterpret_cast<const u32x4a4*>(cmatch + om);
+    st.m1 = *reinterpret_cast<const u32x4a4*>(cmatch + om + 4);
+    st.e = (VIEW == 0 && prior) ? (int32_t)prior[o.op] : -1;
+}
+
+// S streams through once per pass: non-temporal loads / stores, so it does not
+// evict the census rows that neighbouring lines re-read from L2.
+template <int D>
+__device__ __forceinline__ u32x4 load_s(const uint16_t* __restrict__ S, uint32_t opx, int d0)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(S + (size_t)opx * D + d0));
+}
+template <int D>
+__device__ __forceinline__ void store_s(uint16_t* __restrict__ S, uint32_t opx, int d0,
+                                        const uint32_t v[4])
+{
+    __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]},
+                                reinterpret_cast<u32x4*>(S + (size_t)opx * D + d0));
+}
+
+// Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
+// denominator): (den - num) H + num DDC, H = popcount of the census xor, n
+// where the matching pixel leaves the image; DDC from the LDS pattern table
+// (entry d - e + D), a zero run for pixels without prior.
+template <int D, int VIEW>
+__device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, const StepIn& in,
+                                      int x, int d0, uint32_t C[4])
+{
+    uint32_t mc[8];
+    if (VIEW == 0) {
+        mc[0] = in.m1.w; mc[1] = in.m1.z; mc[2] = in.m1.y; mc[3] = in.m1.x;
+        mc[4] = in.m0.w; mc[5] = in.m0.z; mc[6] = in.m0.y; mc[7] = in.m0.x;
+    } else {
+        mc[0] = in.m0.x; mc[1] = in.m0.y; mc[2] = in.m0.z; mc[3] = in.m0.w;
+        mc[4] = in.m1.x; mc[5] = in.m1.y; mc[6] = in.m1.z; mc[7] = in.m1.w;
+    }
+    uint32_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
+    if (VIEW == 0 ? x < d0 + 7 : x + d0 + 7 >= a.W) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool out = VIEW == 0 ? x - d0 - j < 0 : x + d0 + j >= a.W;
+            h[j] = out ? (uint32_t)a.n : h[j];
+        }
+    }
+    if (VIEW == 0) {
+        // values outside [0, D) carry no prior (the ABI only admits -1)
+        const bool has = (unsigned)in.e < (unsigned)D;
+        const uint32_t mulh = (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u;
+        const int sidx = d0 - in.e + D;
+        const int base = has ? ((sidx & 1) ? (D + 8) + ((sidx - 1) >> 1) : (sidx >> 1))
+                             : 2 * (D + 8);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pat[base + i]);
+    } else {
+        const uint32_t mulh = a.mulh_noprior * 0x10001u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, 0u);
+    }
+}
+
+// One step of Eq. 2 on the lane's 8 disparities.  L holds L_r(p - r, .) on
+// entry (ignored when first) and L_r(p, .) on exit; m is the group minimum of
+// L_r(p - r, .) on entry and of L_r(p, .) on exit.
+template <int G>
+__device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t C[4],
+                                     bool first, uint32_t p1x2, uint32_t p2s, bool gfirst,
+                                     bool glast)
+{
+    if (first) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L[i] = C[i];
+    } else {
+        uint32_t pv = dpp<kWaveShr1>(L[3]);   // hi half: cell d0-1
+        uint32_t nx = dpp<kWaveShl1>(L[0]);   // lo half: cell d0+8
+        // ends of the disparity range: reuse the cell itself, which is
+        // already a candidate of the minimum (= leaving the term out)
+        pv = gfirst ? (L[0] << 16) : pv;
+        nx = glast ? (L[3] >> 16) : nx;
+        uint32_t Dm[5];
+        Dm[0] = __builtin_amdgcn_alignbit(L[0], pv, 16);
+        Dm[1] = __builtin_amdgcn_alignbit(L[1], L[0], 16);
+        Dm[2] = __builtin_amdgcn_alignbit(L[2], L[1], 16);
+        Dm[3] = __builtin_amdgcn_alignbit(L[3], L[2], 16);
+        Dm[4] = __builtin_amdgcn_alignbit(nx, L[3], 16);
+        const uint32_t mp2 = (m + p2s) * 0x10001u;
+        const uint32_t mm = m * 0x10001u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
+            uint32_t best = pk_min(pk_min(L[i], nb), mp2);
+            L[i] = pk_add(best, pk_sub(C[i], mm));
+        }
+    }
+    uint32_t mn = pk_min(pk_min(L[0], L[1]), pk_min(L[2], L[3]));
+    m = group_min<G>(min(mn & 0xffffu, mn >> 16));
+}
+
+// Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
+// of (S, d), ties -> smallest d) and the parabola fit through S(d*-1),
+// S(d*), S(d*+1); the owning lane writes d* (and for the left view the
+// subpixel disparity and the learned-check cost features).
+template <int G, int VIEW>
+__device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4], int d0,
+                                         size_t px)
+{
+    constexpr int D = G * 8;
+    uint32_t best = 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t k0 = ((St[i] & 0xffffu) << 9) | (uint32_t)(d0 + 2 * i);
+        uint32_t k1 = ((St[i] >> 16) << 9) | (uint32_t)(d0 + 2 * i + 1);
+        best = min(best, min(k0, k1));
+    }
+    best = group_min<G>(best);
+    const int db = (int)(best & 511u);
+    const uint32_t spv = dpp<kWaveShr1>(St[3]);
+    const uint32_t snx = dpp<kWaveShl1>(St[0]);
+    // learned-check cost feature: second minimum of S over |d - d*| >= 2
+    uint32_t second = 0xffffu;
+    if (VIEW == 0 && a.feat) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d_lo = d0 + 2 * i, d_hi = d_lo + 1;
+            const uint32_t s_lo = St[i] & 0xffffu, s_hi = St[i] >> 16;
+            second = (d_lo - db >= 2 || db - d_lo >= 2) ? min(second, s_lo) : second;
+            second = (d_hi - db >= 2 || db - d_hi >= 2) ? min(second, s_hi) : second;
+        }
+        second = group_min<G>(second);
+    }
+    if (db >= d0 && db < d0 + 8) {
+        a.wta[VIEW][px] = (int16_t)db;
+        if (VIEW == 0) {
+            // cells d0-1 .. d0+8 of S
+            uint32_t c[10];
+            c[0] = spv >> 16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                c[1 + 2 * i] = St[i] & 0xffffu;
+                c[2 + 2 * i] = St[i] >> 16;
+            }
+            c[9] = snx & 0xffffu;
+            const int j = db - d0 + 1;
+            uint32_t A = 0, B = 0, Cc = 0;
+#pragma unroll
+            for (int k = 1; k <= 8; ++k) {
+                if (k == j) {
+                    A = c[k - 1];
+                    B = c[k];
+                    Cc = c[k + 1];
+                }
+            }
+            float v = (float)db;
+            const int den = (int)A - 2 * (int)B + (int)Cc;
+            if (a.subpixel && db > 0 && db < D - 1 && den > 0)
+                v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
+            a.dsub[px] = v;
+            if (a.feat) {
+                a.feat[2 * px] = B | (second << 16);
+                a.feat[2 * px + 1] = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+            }
+        }
+    }
+}
+
+// DDC pattern table in LDS (the Eq. 4 term: 0 at the prior, Q1 at +-1, Q2
+// beyond) as pairs of u16 starting at even (first half) and odd (second
+// half) entries of P[k] = ddc(k - D), k in [0, 2D + 16), followed by a run of
+// zeros used where a pixel has no prior.
+template <int D>
+__device__ __forceinline__ void build_pattern(const SgmArgs& a, uint32_t* pat)
+{
+    for (int i = threadIdx.x; i < 2 * (D + 8) + 4; i += blockDim.x) {
+        uint32_t v[2] = {0u, 0u};
+        if (i < 2 * (D + 8)) {
+            const int half = i >= D + 8;
+            const int k0 = 2 * (i - half * (D + 8)) + half;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                int diff = k0 + j - D;
+                diff = diff < 0 ? -diff : diff;
+                v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+            }
+        }
+        pat[i] = v[0] | (v[1] << 16);
+    }
+}
+
+}  // namespace sldf

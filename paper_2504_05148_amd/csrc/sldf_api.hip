@@ -85,6 +85,13 @@ sldf_status validate(const sldf_params* p)
 // learned check
 bool needs_right(const sldf_params* p) { return p->check_mode == 1 || p->check_mode == 3; }
 
+// Path directions: horizontal and vertical first (4-path set), then the
+// diagonals (8-path set); the 1-path debug mode is left-to-right only.
+const int kDirs[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
+                         {+1, +1}, {-1, +1}, {+1, -1}, {-1, -1}};
+// The same sets as pairs of opposite directions (forward of each pair).
+const int kPairDirs[4][2] = {{+1, 0}, {0, +1}, {+1, +1}, {-1, +1}};
+
 // Workspace plan: one 256-byte aligned segment per array, each holding all
 // batch frames.  Returns the total size; fills b when base != NULL.
 size_t plan(const sldf_params* p, char* base, Buffers* b)
@@ -108,6 +115,16 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* dsub = seg(F * px * 4);
     void* sl = seg(F * cells * 2);
     void* sr = needs_right(p) ? seg(F * cells * 2) : nullptr;
+    // checkpoints of the paired passes: the largest direction pair in use
+    size_t ck_per_fv = 0;
+    for (int k = 0; k < (p->num_paths >= 4 ? p->num_paths / 2 : 0); ++k) {
+        const int dx = kPairDirs[k][0], dy = kPairDirs[k][1];
+        const size_t n = (size_t)num_lines(p->width, p->height, dx, dy) *
+                         (size_t)sgm_pair_ckpt_segs(p->width, p->height, dx, dy) *
+                         (size_t)p->max_disp * 2;
+        ck_per_fv = n > ck_per_fv ? n : ck_per_fv;
+    }
+    void* ck = ck_per_fv ? seg(F * 2 * ck_per_fv) : nullptr;
     void* rb = seg(F * px * (size_t)(p->max_disp / 32) * 4);
     void* rho = seg(F * px * 2);
     void* feat = seg(F * px * 8);
@@ -128,6 +145,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->dsub = (float*)dsub;
         b->S_left = (uint16_t*)sl;
         b->S_right = (uint16_t*)sr;
+        b->ckpt = (uint32_t*)ck;
         b->rowbits = (uint32_t*)rb;
         b->rho = (uint16_t*)rho;
         b->feat = (uint32_t*)feat;
@@ -142,10 +160,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     return off;
 }
 
-// Path directions: horizontal and vertical first (4-path set), then the
-// diagonals (8-path set); the 1-path debug mode is left-to-right only.
-const int kDirs[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
-                         {+1, +1}, {-1, +1}, {+1, -1}, {-1, -1}};
+
 
 }  // namespace
 
@@ -426,17 +441,25 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     // plain check: both views in every launch; learned check: left view
     // here, right view only in the gated fallback below
     const int nviews = ctx->need_right && !learned ? 2 : 1;
+    ga.ckpt = b.ckpt;
     auto sgm_passes = [&](int view_base, int nv, int stage) {
         ga.view_base = view_base;
-        for (int r = 0; r < p.num_paths; ++r) {
-            ga.dx = kDirs[r][0];
-            ga.dy = kDirs[r][1];
+        if (p.num_paths == 1) {
+            ga.dx = kDirs[0][0];
+            ga.dy = kDirs[0][1];
             ga.nlines = num_lines(W, H, ga.dx, ga.dy);
-            int mode = p.num_paths == 1 ? kSingle
-                       : r == 0          ? kFirst
-                       : r == p.num_paths - 1 ? kLast
-                                         : kMiddle;
-            if (launch_sgm_dir(ga, D, mode, nv, n_frames, s) != hipSuccess) return false;
+            if (launch_sgm_dir(ga, D, kSingle, nv, n_frames, s) != hipSuccess) return false;
+            ctx->launches[stage] += 1;
+            return true;
+        }
+        // opposite directions in pairs: S is read-modified-written once per pair
+        const int npairs = p.num_paths / 2;
+        for (int k = 0; k < npairs; ++k) {
+            ga.dx = kPairDirs[k][0];
+            ga.dy = kPairDirs[k][1];
+            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+            const int mode = k == 0 ? kFirst : k == npairs - 1 ? kLast : kMiddle;
+            if (launch_sgm_pair(ga, D, mode, nv, n_frames, s) != hipSuccess) return false;
             ctx->launches[stage] += 1;
         }
         return true;

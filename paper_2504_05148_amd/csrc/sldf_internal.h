@@ -23,6 +23,7 @@ struct Buffers {
     float* dsub;          // [F][H][W]
     uint16_t* S_left;     // [F][H][W][D]
     uint16_t* S_right;    // [F][H][W][D] (only when the stereo check is on)
+    uint32_t* ckpt;       // paired-pass checkpoints, [F * views][lines][segs][D / 2] u32
     uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
     uint16_t* rho;        // [F][H][W] LiDAR residual
     uint32_t* feat;       // [F][H][W][2] surrogate cost features
@@ -83,6 +84,8 @@ struct SgmArgs {
     int32_t subpixel;
     int32_t store_sum;          // last pass also stores S (debug tap)
     uint32_t* feat;             // last left pass: surrogate cost features, or null
+    uint32_t* ckpt;             // paired passes: forward-state checkpoints (scratch)
+    int32_t ckpt_segs;          // checkpoints per line (filled by launch_sgm_pair)
     // fallback gate: when non-null, frame f runs only if gate[f] > gate_limit
     const int32_t* gate;
     int32_t gate_limit;
@@ -210,6 +213,10 @@ hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s);
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
+// two opposite directions (dx, dy) and (-dx, -dy) in one launch
+hipError_t launch_sgm_pair(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+                           hipStream_t s);
+int64_t sgm_pair_ckpt_segs(int W, int H, int dx, int dy);
 hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s);
 hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s);
 hipError_t launch_quantize(const float* in, int W, int H, int in_pitch, int D,
