@@ -28,7 +28,7 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
     const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
     const int16_t* __restrict__ prior =
-        VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
+        VIEW == 0 ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
     uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
     const uint32_t p1x2 = a.p1s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;

@@ -4,9 +4,9 @@
 //
 // Opposite directions walk the same lines in opposite orders.  For each line
 // (owned by G = D / 8 lanes, see sgm_common.h):
-//   1. the forward direction r runs over the whole line and stores its
-//      state L_r every kSeg pixels (a checkpoint per segment, 1 / kSeg of
-//      the cost volume) in a scratch buffer;
+//   1. the forward direction r runs over the line and stores its state L_r
+//      every kSeg pixels (a checkpoint per segment, 1 / kSeg of the cost
+//      volume) in a scratch buffer;
 //   2. the segments are then visited from the last to the first: the
 //      forward states of the segment are recomputed from the checkpoint into
 //      registers (with the joint costs of its pixels), and the backward
@@ -34,7 +34,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
     const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
     const int16_t* __restrict__ prior =
-        VIEW == 0 && a.prior ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
+        VIEW == 0 ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
     uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
     uint32_t* __restrict__ ck =
         a.ckpt + (((size_t)fv * a.nlines + line) * a.ckpt_segs * G + g) * 4;
@@ -45,101 +45,96 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     const uint32_t dpx = (uint32_t)(a.dy * a.W + a.dx);
     const PixOff o0{(uint32_t)(y0 * a.census_pitch + x0 + D), (uint32_t)(y0 * a.prior_pitch + x0),
                     (uint32_t)(y0 * a.W + x0)};
-    auto pix = [&](int t) {
-        return PixOff{o0.oc + (uint32_t)t * dc, o0.op + (uint32_t)t * dp,
-                      o0.opx + (uint32_t)t * dpx};
-    };
-    auto load = [&](StepIn& b, int t) { load_pixel<D, VIEW>(cbase, cmatch, prior, pix(t), d0, b); };
 
-    // ---- 1. forward direction over the whole line, checkpoints ----
+    // The line is cut into nseg segments of kSeg positions; `pad` virtual
+    // positions before pixel 0 fill the first one.  Position u maps to pixel
+    // t = u - pad.  Virtual positions have cost 0 (see cost8) and load pixel
+    // 0, so every step below runs unconditionally; only S stores and the
+    // WTA are skipped for them.
+    const int nseg = (len + kSeg - 1) / kSeg;
+    const int pad = nseg * kSeg - len;
+    auto pix = [&](int u) {
+        const uint32_t t = (uint32_t)max(u - pad, 0);
+        return PixOff{o0.oc + t * dc, o0.op + t * dp, o0.opx + t * dpx};
+    };
+    auto load = [&](StepIn& b, int u) { load_pixel<D, VIEW>(cbase, cmatch, prior, pix(u), d0, b); };
+    auto cost = [&](const StepIn& in, int u, uint32_t C[4]) {
+        cost8<D, VIEW>(a, pat, in, x0 + (u - pad) * a.dx, d0, C, u >= pad);
+    };
+    auto ckpt = [&](int q) { return reinterpret_cast<u32x4*>(ck + (size_t)q * G * 4); };
+
+    // ---- 1. forward direction r over segments 0 .. nseg-2, checkpoints ----
+    // R[j] holds the inputs of position kSeg q + j; each is reloaded for the
+    // next segment as soon as it has been used.
+    StepIn R[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) load(R[j], j);
     {
         uint32_t L[4] = {0, 0, 0, 0};
         uint32_t m = 0;
-        auto fstep = [&](const StepIn& in, int t) {
-            uint32_t C[4];
-            cost8<D, VIEW>(a, pat, in, x0 + t * a.dx, d0, C);
-            rec8<G>(L, m, C, t == 0, p1x2, a.p2s, gfirst, glast);
-            if ((t + 1) % kSeg == 0 && t + 1 < len)
-                *reinterpret_cast<u32x4*>(ck + (size_t)((t + 1) / kSeg - 1) * G * 4) =
-                    u32x4{L[0], L[1], L[2], L[3]};
-        };
-        StepIn b0, b1, b2;
-        load(b0, 0);
-        if (len > 1) load(b1, 1);
-        if (len > 2) load(b2, 2);
-        for (int t = 0; t < len; t += 3) {
-            fstep(b0, t);
-            if (t + 3 < len) load(b0, t + 3);
-            if (t + 1 >= len) break;
-            fstep(b1, t + 1);
-            if (t + 4 < len) load(b1, t + 4);
-            if (t + 2 >= len) break;
-            fstep(b2, t + 2);
-            if (t + 5 < len) load(b2, t + 5);
+        for (int q = 0; q < nseg - 1; ++q) {
+#pragma unroll
+            for (int j = 0; j < kSeg; ++j) {
+                uint32_t C[4];
+                cost(R[j], q * kSeg + j, C);
+                load(R[j], (q + 1) * kSeg + j);
+                rec8<G>(L, m, C, false, p1x2, a.p2s, gfirst, glast);
+            }
+            *ckpt(q) = u32x4{L[0], L[1], L[2], L[3]};
         }
     }
 
-    // ---- 2. segments from the end: recompute forward, walk backward ----
-    // Software pipeline: while segment s is walked backward, the census and
-    // checkpoint of segment s - 1 are already in flight, and each S slot is
-    // refilled with the S of segment s - 1 as soon as it has been consumed.
-    // Only the last segment can be shorter than kSeg.
-    const int nseg = (len + kSeg - 1) / kSeg;
+    // ---- 2. segments from the last to the first ----
+    // The forward states of a segment are recomputed from its checkpoint;
+    // the backward direction -r then walks the segment in reverse and adds
+    // L_r + L_-r into S (or takes the WTA).  While segment s is walked, the
+    // inputs, checkpoint and S of segment s - 1 are already in flight.
+    u32x4 Sin[kSeg];
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+        Sin[j] = kLoadS ? load_s<D>(S, pix((nseg - 1) * kSeg + j).opx, d0) : u32x4{0u, 0u, 0u, 0u};
+    // forward state entering a segment: its checkpoint (zero for the first
+    // segment), with the group minimum; prepared one iteration ahead
+    uint32_t Ln[4], mn;
+    auto enter = [&](const u32x4& c, bool zero) {
+        Ln[0] = zero ? 0u : c.x; Ln[1] = zero ? 0u : c.y;
+        Ln[2] = zero ? 0u : c.z; Ln[3] = zero ? 0u : c.w;
+        const uint32_t v = pk_min(pk_min(Ln[0], Ln[1]), pk_min(Ln[2], Ln[3]));
+        mn = group_min<G>(min(v & 0xffffu, v >> 16));
+    };
+    enter(*ckpt(max(nseg - 2, 0)), nseg == 1);
     uint32_t Lb[4] = {0, 0, 0, 0};
     uint32_t mb = 0;
-    StepIn R[kSeg];
-    u32x4 Sin[kSeg];
-    u32x4 cin = u32x4{0u, 0u, 0u, 0u};
-    {
-        const int t0 = (nseg - 1) * kSeg;
-        const int tl = len - t0;
-#pragma unroll
-        for (int j = 0; j < kSeg; ++j)
-            if (j < tl) load(R[j], t0 + j);
-        if (nseg > 1) cin = *reinterpret_cast<const u32x4*>(ck + (size_t)(nseg - 2) * G * 4);
-#pragma unroll
-        for (int j = 0; j < kSeg; ++j) {
-            Sin[j] = u32x4{0u, 0u, 0u, 0u};
-            if (kLoadS && j < tl) Sin[j] = load_s<D>(S, pix(t0 + j).opx, d0);
-        }
-    }
     for (int s = nseg - 1; s >= 0; --s) {
-        const int t0 = s * kSeg;
-        const int tl = min(kSeg, len - t0);
-        uint32_t Lf[4] = {cin.x, cin.y, cin.z, cin.w};
-        uint32_t mf = 0;
-        if (s > 0) {
-            const uint32_t mn = pk_min(pk_min(Lf[0], Lf[1]), pk_min(Lf[2], Lf[3]));
-            mf = group_min<G>(min(mn & 0xffffu, mn >> 16));
-        }
+        const int u0 = s * kSeg;
+        // issued first in the iteration (and kept there), so that every load
+        // after it may still be in flight when it is consumed at the end
+        const u32x4 cin = *ckpt(max(s - 2, 0));
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t Lf[4] = {Ln[0], Ln[1], Ln[2], Ln[3]};
+        uint32_t mf = mn;
         uint32_t Cb[kSeg][4], Lbuf[kSeg][4];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            if (j < tl) {
-                cost8<D, VIEW>(a, pat, R[j], x0 + (t0 + j) * a.dx, d0, Cb[j]);
-                rec8<G>(Lf, mf, Cb[j], s == 0 && j == 0, p1x2, a.p2s, gfirst, glast);
+            cost(R[j], u0 + j, Cb[j]);
+            load(R[j], u0 - kSeg + j);
+            rec8<G>(Lf, mf, Cb[j], false, p1x2, a.p2s, gfirst, glast);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
-            }
-        }
-        if (s > 0) {
-#pragma unroll
-            for (int j = 0; j < kSeg; ++j) load(R[j], t0 - kSeg + j);
-            if (s > 1) cin = *reinterpret_cast<const u32x4*>(ck + (size_t)(s - 2) * G * 4);
+            for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
         }
 #pragma unroll
         for (int j = kSeg - 1; j >= 0; --j) {
-            if (j < tl) {
-                // the backward direction starts at the last pixel of the line
-                rec8<G>(Lb, mb, Cb[j], s == nseg - 1 && j == tl - 1, p1x2, a.p2s, gfirst, glast);
-                uint32_t St[4];
+            rec8<G>(Lb, mb, Cb[j], false, p1x2, a.p2s, gfirst, glast);
+            uint32_t St[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);
-                if (kLoadS) {
-                    St[0] = pk_add(St[0], Sin[j].x); St[1] = pk_add(St[1], Sin[j].y);
-                    St[2] = pk_add(St[2], Sin[j].z); St[3] = pk_add(St[3], Sin[j].w);
-                }
-                const uint32_t opx = pix(t0 + j).opx;
+            for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);
+            if (kLoadS) {
+                St[0] = pk_add(St[0], Sin[j].x); St[1] = pk_add(St[1], Sin[j].y);
+                St[2] = pk_add(St[2], Sin[j].z); St[3] = pk_add(St[3], Sin[j].w);
+            }
+            const int u = u0 + j;
+            const uint32_t opx = pix(u).opx;
+            if (u >= pad) {
                 if (kStoreS) {
                     store_s<D>(S, opx, d0, St);
                 } else {
@@ -147,10 +142,9 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                     wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + opx);
                 }
             }
-            // every slot of segment s - 1 is refilled, also those a short
-            // last segment left unused
-            if (kLoadS && s > 0) Sin[j] = load_s<D>(S, pix(t0 - kSeg + j).opx, d0);
+            if (kLoadS) Sin[j] = load_s<D>(S, pix(u - kSeg).opx, d0);
         }
+        enter(cin, s == 1);
     }
 }
 

@@ -112,7 +112,7 @@ __device__ __forceinline__ void load_pixel(const uint32_t* __restrict__ cbase,
     const uint32_t om = VIEW == 0 ? o.oc - (uint32_t)(d0 + 7) : o.oc + (uint32_t)d0;
     st.m0 = *reinterpret_cast<const u32x4a4*>(cmatch + om);
     st.m1 = *reinterpret_cast<const u32x4a4*>(cmatch + om + 4);
-    st.e = (VIEW == 0 && prior) ? (int32_t)prior[o.op] : -1;
+    st.e = VIEW == 0 ? (int32_t)prior[o.op] : -1;   // the left view always has a prior map
 }
 
 // S streams through once per pass: non-temporal loads / stores, so it does not
@@ -133,10 +133,13 @@ __device__ __forceinline__ void store_s(uint16_t* __restrict__ S, uint32_t opx, 
 // Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
 // denominator): (den - num) H + num DDC, H = popcount of the census xor, n
 // where the matching pixel leaves the image; DDC from the LDS pattern table
-// (entry d - e + D), a zero run for pixels without prior.
+// (entry d - e + D), a zero run for pixels without prior.  A pixel that is
+// not `real` (padding before the start of a line) gets cost 0: from a zero
+// state L = 0, m = 0 such a step leaves the state at zero, so the first real
+// pixel then yields L = C as Eq. 2 starts a path.
 template <int D, int VIEW>
 __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, const StepIn& in,
-                                      int x, int d0, uint32_t C[4])
+                                      int x, int d0, uint32_t C[4], bool real = true)
 {
     uint32_t mc[8];
     if (VIEW == 0) {
@@ -158,8 +161,9 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
     }
     if (VIEW == 0) {
         // values outside [0, D) carry no prior (the ABI only admits -1)
-        const bool has = (unsigned)in.e < (unsigned)D;
-        const uint32_t mulh = (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u;
+        const bool has = real && (unsigned)in.e < (unsigned)D;
+        const uint32_t mulh =
+            real ? (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u : 0u;
         const int sidx = d0 - in.e + D;
         const int base = has ? ((sidx & 1) ? (D + 8) + ((sidx - 1) >> 1) : (sidx >> 1))
                              : 2 * (D + 8);
@@ -167,7 +171,7 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
         for (int i = 0; i < 4; ++i)
             C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pat[base + i]);
     } else {
-        const uint32_t mulh = a.mulh_noprior * 0x10001u;
+        const uint32_t mulh = real ? a.mulh_noprior * 0x10001u : 0u;
 #pragma unroll
         for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, 0u);
     }
