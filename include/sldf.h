@@ -68,7 +68,9 @@ typedef struct {
     int32_t struct_size;   /* sizeof(sldf_params): ABI check */
     int32_t width;         /* W, 16 <= W <= 4096 */
     int32_t height;        /* H, 16 <= H <= 4096 */
-    int32_t max_disp;      /* D, disparities 0..D-1; D in {64, 128, 256} */
+    int32_t max_disp;      /* D, disparities 0..D-1; D in {64, 128, 256};
+                              W * H * D <= 2^31 (one frame's cost volume is
+                              addressed with 32-bit byte offsets) */
     int32_t census_w;      /* odd census window width  (<= 15) */
     int32_t census_h;      /* odd census window height (<= 15);
                               (census_w * census_h - 1) / 2 <= 32 bits */
@@ -171,12 +173,14 @@ sldf_status sldf_set_taps(sldf_ctx* ctx, const sldf_taps* taps);
 
 /* Process one frame (the whole method, Fig. 1 flow).  All pointers device:
      left, right  uint8 [H][img_pitch], 16-byte aligned, img_pitch % 16 == 0
-     lidar        int16 [H][lidar_pitch], D-bar: 0..D-1 or -1 (= invalid), as
-                  written by sldf_lidar_quantize; other values are outside the
-                  contract (memory-safe, result unspecified)
+     lidar        int16 [H][lidar_pitch], W <= lidar_pitch <= 65536, D-bar:
+                  0..D-1 or -1 (= invalid), as written by sldf_lidar_quantize;
+                  other values are outside the contract (memory-safe, result
+                  unspecified)
      disp_out     float [H][out_pitch]: subpixel disparity, -1.0f if invalid
      valid_out    uint8 [H][out_pitch]: 1 = consistent (Eq. 6), 0 = invalid
-   Enqueue-only on hip_stream.  Errors: EINVAL (NULL pointer / pitch < W),
+   Enqueue-only on hip_stream.  Errors: EINVAL (NULL pointer / pitch < W /
+   lidar_pitch > 65536),
    EALIGN, EDEVICE (launch failure). */
 sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
                      int32_t img_pitch, const int16_t* lidar, int32_t lidar_pitch,

@@ -23,38 +23,22 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     int x0, y0, len;
     line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
-    // census rows are addressed from their padded start (pixel x at x + D),
-    // so every offset below is non-negative
-    const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
-    const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
-    const int16_t* __restrict__ prior =
-        VIEW == 0 ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
-    uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
-    const uint32_t p1x2 = a.p1s * 0x10001u;
+    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0);
+    const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
-    const uint32_t dc = (uint32_t)(a.dy * a.census_pitch + a.dx);
-    const uint32_t dp = (uint32_t)(a.dy * a.prior_pitch + a.dx);
-    const uint32_t dpx = (uint32_t)(a.dy * a.W + a.dx);
-    PixOff ol{(uint32_t)(y0 * a.census_pitch + x0 + D), (uint32_t)(y0 * a.prior_pitch + x0),
-              (uint32_t)(y0 * a.W + x0)};   // next load
-    PixOff oc = ol;                         // step being computed
-    auto adv = [&](PixOff& o) {
-        o.oc += dc;
-        o.op += dp;
-        o.opx += dpx;
-    };
-    uint32_t L[4] = {0, 0, 0, 0};
+    uint32_t L[4] = {0, 0, 0, 0};   // zero state: the first step yields L = C
     uint32_t m = 0;
     auto step = [&](const StepIn& in, const u32x4& s_in, int t) {
         uint32_t C[4];
         cost8<D, VIEW>(a, pat, in, x0 + t * a.dx, d0, C);
-        rec8<G>(L, m, C, t == 0, p1x2, a.p2s, gfirst, glast);
+        rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast);
+        const PixOff o = la.at(t);
         if (MODE == kFirst) {
-            store_s<D>(S, oc.opx, d0, L);
+            store_s(la, o, L);
         } else if (MODE == kMiddle) {
-            uint32_t o[4] = {pk_add(s_in.x, L[0]), pk_add(s_in.y, L[1]), pk_add(s_in.z, L[2]),
+            uint32_t v[4] = {pk_add(s_in.x, L[0]), pk_add(s_in.y, L[1]), pk_add(s_in.z, L[2]),
                              pk_add(s_in.w, L[3])};
-            store_s<D>(S, oc.opx, d0, o);
+            store_s(la, o, v);
         } else {
             uint32_t St[4];
             if (MODE == kLast) {
@@ -64,37 +48,32 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
 #pragma unroll
                 for (int i = 0; i < 4; ++i) St[i] = L[i];
             }
-            if (a.store_sum) store_s<D>(S, oc.opx, d0, St);
-            wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + oc.opx);
+            if (a.store_sum) store_s(la, o, St);
+            const uint32_t px = (uint32_t)((y0 + t * a.dy) * a.W + x0 + t * a.dx);
+            wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px);
         }
-        adv(oc);
     };
     // three steps in flight: the loads of step t+3 are issued once step t
     // has consumed its buffer
     StepIn b0, b1, b2;
     u32x4 s0 = {}, s1 = {}, s2 = {};
-    auto load = [&](StepIn& b, u32x4& sv) {
-        load_pixel<D, VIEW>(cbase, cmatch, prior, ol, d0, b);
-        if (kLoadS) sv = load_s<D>(S, ol.opx, d0);
+    auto load = [&](StepIn& b, u32x4& sv, int t) {
+        const PixOff o = la.at(t);
+        load_pixel<VIEW>(la, o, b);
+        if (kLoadS) sv = load_s(la, o);
     };
-    load(b0, s0);
-    adv(ol);
-    if (len > 1) load(b1, s1);
-    adv(ol);
-    if (len > 2) load(b2, s2);
-    adv(ol);
+    load(b0, s0, 0);
+    if (len > 1) load(b1, s1, 1);
+    if (len > 2) load(b2, s2, 2);
     for (int t = 0; t < len; t += 3) {
         step(b0, s0, t);
-        if (t + 3 < len) load(b0, s0);
-        adv(ol);
+        if (t + 3 < len) load(b0, s0, t + 3);
         if (t + 1 >= len) break;
         step(b1, s1, t + 1);
-        if (t + 4 < len) load(b1, s1);
-        adv(ol);
+        if (t + 4 < len) load(b1, s1, t + 4);
         if (t + 2 >= len) break;
         step(b2, s2, t + 2);
-        if (t + 5 < len) load(b2, s2);
-        adv(ol);
+        if (t + 5 < len) load(b2, s2, t + 5);
     }
 }
 

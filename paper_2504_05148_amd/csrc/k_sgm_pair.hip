@@ -31,20 +31,11 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     int x0, y0, len;
     line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
-    const uint32_t* __restrict__ cbase = a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride;
-    const uint32_t* __restrict__ cmatch = a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride;
-    const int16_t* __restrict__ prior =
-        VIEW == 0 ? a.prior + (int64_t)frame * a.prior_fstride : nullptr;
-    uint16_t* __restrict__ S = a.S[VIEW] + (int64_t)frame * a.S_stride;
+    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0);
     uint32_t* __restrict__ ck =
         a.ckpt + (((size_t)fv * a.nlines + line) * a.ckpt_segs * G + g) * 4;
-    const uint32_t p1x2 = a.p1s * 0x10001u;
+    const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
-    const uint32_t dc = (uint32_t)(a.dy * a.census_pitch + a.dx);
-    const uint32_t dp = (uint32_t)(a.dy * a.prior_pitch + a.dx);
-    const uint32_t dpx = (uint32_t)(a.dy * a.W + a.dx);
-    const PixOff o0{(uint32_t)(y0 * a.census_pitch + x0 + D), (uint32_t)(y0 * a.prior_pitch + x0),
-                    (uint32_t)(y0 * a.W + x0)};
 
     // The line is cut into nseg segments of kSeg positions; `pad` virtual
     // positions before pixel 0 fill the first one.  Position u maps to pixel
@@ -53,11 +44,8 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     // WTA are skipped for them.
     const int nseg = (len + kSeg - 1) / kSeg;
     const int pad = nseg * kSeg - len;
-    auto pix = [&](int u) {
-        const uint32_t t = (uint32_t)max(u - pad, 0);
-        return PixOff{o0.oc + t * dc, o0.op + t * dp, o0.opx + t * dpx};
-    };
-    auto load = [&](StepIn& b, int u) { load_pixel<D, VIEW>(cbase, cmatch, prior, pix(u), d0, b); };
+    auto pix = [&](int u) { return la.at(max(u - pad, 0)); };
+    auto load = [&](StepIn& b, int u) { load_pixel<VIEW>(la, pix(u), b); };
     auto cost = [&](const StepIn& in, int u, uint32_t C[4]) {
         cost8<D, VIEW>(a, pat, in, x0 + (u - pad) * a.dx, d0, C, u >= pad);
     };
@@ -78,7 +66,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                 uint32_t C[4];
                 cost(R[j], q * kSeg + j, C);
                 load(R[j], (q + 1) * kSeg + j);
-                rec8<G>(L, m, C, false, p1x2, a.p2s, gfirst, glast);
+                rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast);
             }
             *ckpt(q) = u32x4{L[0], L[1], L[2], L[3]};
         }
@@ -92,15 +80,14 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     u32x4 Sin[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j)
-        Sin[j] = kLoadS ? load_s<D>(S, pix((nseg - 1) * kSeg + j).opx, d0) : u32x4{0u, 0u, 0u, 0u};
+        Sin[j] = kLoadS ? load_s(la, pix((nseg - 1) * kSeg + j)) : u32x4{0u, 0u, 0u, 0u};
     // forward state entering a segment: its checkpoint (zero for the first
     // segment), with the group minimum; prepared one iteration ahead
     uint32_t Ln[4], mn;
     auto enter = [&](const u32x4& c, bool zero) {
         Ln[0] = zero ? 0u : c.x; Ln[1] = zero ? 0u : c.y;
         Ln[2] = zero ? 0u : c.z; Ln[3] = zero ? 0u : c.w;
-        const uint32_t v = pk_min(pk_min(Ln[0], Ln[1]), pk_min(Ln[2], Ln[3]));
-        mn = group_min<G>(min(v & 0xffffu, v >> 16));
+        mn = group_min<G>(lane_min2(Ln));
     };
     enter(*ckpt(max(nseg - 2, 0)), nseg == 1);
     uint32_t Lb[4] = {0, 0, 0, 0};
@@ -118,13 +105,13 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
         for (int j = 0; j < kSeg; ++j) {
             cost(R[j], u0 + j, Cb[j]);
             load(R[j], u0 - kSeg + j);
-            rec8<G>(Lf, mf, Cb[j], false, p1x2, a.p2s, gfirst, glast);
+            rec8<G>(Lf, mf, Cb[j], p1x2, p2x2, gfirst, glast);
 #pragma unroll
             for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
         }
 #pragma unroll
         for (int j = kSeg - 1; j >= 0; --j) {
-            rec8<G>(Lb, mb, Cb[j], false, p1x2, a.p2s, gfirst, glast);
+            rec8<G>(Lb, mb, Cb[j], p1x2, p2x2, gfirst, glast);
             uint32_t St[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);
@@ -133,16 +120,18 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                 St[2] = pk_add(St[2], Sin[j].z); St[3] = pk_add(St[3], Sin[j].w);
             }
             const int u = u0 + j;
-            const uint32_t opx = pix(u).opx;
             if (u >= pad) {
+                const PixOff o = la.at(u - pad);
                 if (kStoreS) {
-                    store_s<D>(S, opx, d0, St);
+                    store_s(la, o, St);
                 } else {
-                    if (a.store_sum) store_s<D>(S, opx, d0, St);
-                    wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + opx);
+                    if (a.store_sum) store_s(la, o, St);
+                    const int t = u - pad;
+                    const uint32_t px = (uint32_t)((y0 + t * a.dy) * a.W + x0 + t * a.dx);
+                    wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px);
                 }
             }
-            if (kLoadS) Sin[j] = load_s<D>(S, pix(u - kSeg).opx, d0);
+            if (kLoadS) Sin[j] = load_s(la, pix(u - kSeg));
         }
         enter(cin, s == 1);
     }

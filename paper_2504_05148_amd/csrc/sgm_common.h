@@ -35,6 +35,8 @@ constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 constexpr int kWaveShr1 = 0x138;       // lane i <- lane i-1
 constexpr int kWaveShl1 = 0x130;       // lane i <- lane i+1
+constexpr int kRowShr1 = 0x111;        // lane i <- lane i-1 within a row of 16
+constexpr int kRowShl1 = 0x101;        // lane i <- lane i+1 within a row of 16
 
 constexpr int kXcds = 8;               // MI355X: 8 XCDs, one L2 each
 
@@ -95,39 +97,80 @@ struct StepIn {
     int32_t e;          // prior disparity (-1 = none)
 };
 
-// Offsets of one pixel: census (padded rows, pixel x at x + D), prior, pixel.
+// Byte offsets of one pixel for one lane: census of the base pixel, census
+// of the lane's first matching pixel, prior, the lane's 8 cells of S.
 struct PixOff {
-    uint32_t oc, op, opx;
+    uint32_t oc, om, op, os;
+};
+
+// Addressing of one line for one lane.  The bases are uniform over the
+// workgroup (one frame-view), the offsets 32-bit byte offsets, so every load
+// is a scalar base plus a vector offset.  Pixel t of the line sits at
+// offset0 + t * step; the steps are small signed values (24-bit products).
+struct LineAddr {
+    const char* cbase;      // census of the base view, padded row starts
+    const char* cmatch;     // census of the matching view
+    const char* prior;      // prior map (left view)
+    char* S;                // aggregated cost
+    uint32_t oc0, om0, op0, os0;
+    int32_t dc, dp, ds;
+
+    __device__ __forceinline__ PixOff at(int t) const
+    {
+        const uint32_t c = (uint32_t)__mul24(t, dc);
+        return PixOff{oc0 + c, om0 + c, op0 + (uint32_t)__mul24(t, dp),
+                      os0 + (uint32_t)__mul24(t, ds)};
+    }
 };
 
 template <int D, int VIEW>
-__device__ __forceinline__ void load_pixel(const uint32_t* __restrict__ cbase,
-                                           const uint32_t* __restrict__ cmatch,
-                                           const int16_t* __restrict__ prior, const PixOff& o,
-                                           int d0, StepIn& st)
+__device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x0, int y0,
+                                              int d0)
 {
-    st.cb = cbase[o.oc];
+    LineAddr la;
+    // census rows are addressed from their padded start (pixel x at x + D),
+    // so every offset is non-negative
+    la.cbase = reinterpret_cast<const char*>(a.cbase[VIEW] - D +
+                                             (int64_t)frame * a.census_fstride);
+    la.cmatch = reinterpret_cast<const char*>(a.cmatch[VIEW] - D +
+                                              (int64_t)frame * a.census_fstride);
+    la.prior = VIEW == 0 ? reinterpret_cast<const char*>(a.prior +
+                                                         (int64_t)frame * a.prior_fstride)
+                         : nullptr;
+    la.S = reinterpret_cast<char*>(a.S[VIEW] + (int64_t)frame * a.S_stride);
+    la.oc0 = (uint32_t)(y0 * a.census_pitch + x0 + D) * 4u;
     // matching pixels: x - d (left base, descending) or x + d (right base)
     // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
-    const uint32_t om = VIEW == 0 ? o.oc - (uint32_t)(d0 + 7) : o.oc + (uint32_t)d0;
-    st.m0 = *reinterpret_cast<const u32x4a4*>(cmatch + om);
-    st.m1 = *reinterpret_cast<const u32x4a4*>(cmatch + om + 4);
-    st.e = VIEW == 0 ? (int32_t)prior[o.op] : -1;   // the left view always has a prior map
+    la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + 7) * 4u : la.oc0 + (uint32_t)d0 * 4u;
+    la.op0 = (uint32_t)(y0 * a.prior_pitch + x0) * 2u;
+    la.os0 = ((uint32_t)(y0 * a.W + x0) * D + (uint32_t)d0) * 2u;
+    la.dc = (a.dy * a.census_pitch + a.dx) * 4;
+    la.dp = (a.dy * a.prior_pitch + a.dx) * 2;
+    la.ds = (a.dy * a.W + a.dx) * D * 2;
+    return la;
+}
+
+template <int VIEW>
+__device__ __forceinline__ void load_pixel(const LineAddr& la, const PixOff& o, StepIn& st)
+{
+    st.cb = *reinterpret_cast<const uint32_t*>(la.cbase + o.oc);
+    const char* pm = la.cmatch + o.om;
+    st.m0 = *reinterpret_cast<const u32x4a4*>(pm);
+    st.m1 = *reinterpret_cast<const u32x4a4*>(pm + 16);
+    // the left view always has a prior map
+    st.e = VIEW == 0 ? (int32_t) * reinterpret_cast<const int16_t*>(la.prior + o.op) : -1;
 }
 
 // S streams through once per pass: non-temporal loads / stores, so it does not
 // evict the census rows that neighbouring lines re-read from L2.
-template <int D>
-__device__ __forceinline__ u32x4 load_s(const uint16_t* __restrict__ S, uint32_t opx, int d0)
+__device__ __forceinline__ u32x4 load_s(const LineAddr& la, const PixOff& o)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(S + (size_t)opx * D + d0));
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(la.S + o.os));
 }
-template <int D>
-__device__ __forceinline__ void store_s(uint16_t* __restrict__ S, uint32_t opx, int d0,
-                                        const uint32_t v[4])
+__device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, const uint32_t v[4])
 {
     __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]},
-                                reinterpret_cast<u32x4*>(S + (size_t)opx * D + d0));
+                                reinterpret_cast<u32x4*>(la.S + o.os));
 }
 
 // Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
@@ -164,9 +207,10 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
         const bool has = real && (unsigned)in.e < (unsigned)D;
         const uint32_t mulh =
             real ? (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u : 0u;
-        const int sidx = d0 - in.e + D;
-        const int base = has ? ((sidx & 1) ? (D + 8) + ((sidx - 1) >> 1) : (sidx >> 1))
-                             : 2 * (D + 8);
+        // entry d0 - e + D (>= 1 with a prior): odd entries start in the
+        // second half of the table
+        const int sidx = (d0 + D) - in.e;
+        const int base = has ? (sidx >> 1) + ((sidx & 1) ? D + 8 : 0) : 2 * (D + 8);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pat[base + i]);
@@ -177,41 +221,50 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
     }
 }
 
+// Minimum of the lane's 8 cells, in both halves of the result.
+__device__ __forceinline__ uint32_t lane_min2(const uint32_t L[4])
+{
+    const uint32_t v = pk_min(pk_min(L[0], L[1]), pk_min(L[2], L[3]));
+    return pk_min(v, __builtin_amdgcn_alignbit(v, v, 16));
+}
+
 // One step of Eq. 2 on the lane's 8 disparities.  L holds L_r(p - r, .) on
-// entry (ignored when first) and L_r(p, .) on exit; m is the group minimum of
-// L_r(p - r, .) on entry and of L_r(p, .) on exit.
+// entry and L_r(p, .) on exit; m is the group minimum of L_r(p - r, .) on
+// entry and of L_r(p, .) on exit, held in both u16 halves.  A path starts
+// from L = 0, m = 0: the first step then yields L = C.
 template <int G>
 __device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t C[4],
-                                     bool first, uint32_t p1x2, uint32_t p2s, bool gfirst,
-                                     bool glast)
+                                     uint32_t p1x2, uint32_t p2x2, bool gfirst, bool glast)
 {
-    if (first) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) L[i] = C[i];
+    // neighbour cells d0-1 (hi half of pv) and d0+8 (lo half of nx); at the
+    // ends of the disparity range the term is left out of the minimum
+    uint32_t pv, nx;
+    if (G == 16) {
+        // a group is one DPP row: lanes outside the row read as 0xffff, which
+        // never wins the neighbour minimum (the other neighbour is in range)
+        pv = __builtin_amdgcn_update_dpp(0xffffffffu, L[3], kRowShr1, 0xf, 0xf, false);
+        nx = __builtin_amdgcn_update_dpp(0xffffffffu, L[0], kRowShl1, 0xf, 0xf, false);
     } else {
-        uint32_t pv = dpp<kWaveShr1>(L[3]);   // hi half: cell d0-1
-        uint32_t nx = dpp<kWaveShl1>(L[0]);   // lo half: cell d0+8
-        // ends of the disparity range: reuse the cell itself, which is
-        // already a candidate of the minimum (= leaving the term out)
+        pv = dpp<kWaveShr1>(L[3]);
+        nx = dpp<kWaveShl1>(L[0]);
+        // reuse the cell itself, already a candidate of the minimum
         pv = gfirst ? (L[0] << 16) : pv;
         nx = glast ? (L[3] >> 16) : nx;
-        uint32_t Dm[5];
-        Dm[0] = __builtin_amdgcn_alignbit(L[0], pv, 16);
-        Dm[1] = __builtin_amdgcn_alignbit(L[1], L[0], 16);
-        Dm[2] = __builtin_amdgcn_alignbit(L[2], L[1], 16);
-        Dm[3] = __builtin_amdgcn_alignbit(L[3], L[2], 16);
-        Dm[4] = __builtin_amdgcn_alignbit(nx, L[3], 16);
-        const uint32_t mp2 = (m + p2s) * 0x10001u;
-        const uint32_t mm = m * 0x10001u;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
-            uint32_t best = pk_min(pk_min(L[i], nb), mp2);
-            L[i] = pk_add(best, pk_sub(C[i], mm));
-        }
     }
-    uint32_t mn = pk_min(pk_min(L[0], L[1]), pk_min(L[2], L[3]));
-    m = group_min<G>(min(mn & 0xffffu, mn >> 16));
+    uint32_t Dm[5];
+    Dm[0] = __builtin_amdgcn_alignbit(L[0], pv, 16);
+    Dm[1] = __builtin_amdgcn_alignbit(L[1], L[0], 16);
+    Dm[2] = __builtin_amdgcn_alignbit(L[2], L[1], 16);
+    Dm[3] = __builtin_amdgcn_alignbit(L[3], L[2], 16);
+    Dm[4] = __builtin_amdgcn_alignbit(nx, L[3], 16);
+    const uint32_t mp2 = pk_add(m, p2x2);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
+        uint32_t best = pk_min(pk_min(L[i], nb), mp2);
+        L[i] = pk_add(best, pk_sub(C[i], m));
+    }
+    m = group_min<G>(lane_min2(L));
 }
 
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum

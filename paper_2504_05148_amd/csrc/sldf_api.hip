@@ -50,6 +50,8 @@ sldf_status validate(const sldf_params* p)
     if (p->width < 16 || p->width > 4096 || p->height < 16 || p->height > 4096)
         return SLDF_ESHAPE;
     if (p->max_disp != 64 && p->max_disp != 128 && p->max_disp != 256) return SLDF_ESHAPE;
+    // the path passes address one frame's cost volume with 32-bit byte offsets
+    if ((int64_t)p->width * p->height * p->max_disp > ((int64_t)1 << 31)) return SLDF_ESHAPE;
     if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1) ||
         p->census_w > 15 || p->census_h > 15)
         return SLDF_EINVAL;
@@ -330,6 +332,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (!left || !right || !lidar || !disp_out || !valid_out) return SLDF_EINVAL;
     if (img_pitch < p.width || lidar_pitch < p.width || out_pitch < p.width)
         return SLDF_EINVAL;
+    // the path passes address the prior map with 32-bit byte offsets
+    if (lidar_pitch > 65536) return SLDF_EINVAL;
     if (n_frames > 1) {
         if (img_frame_stride < (int64_t)img_pitch * p.height ||
             lidar_frame_stride < (int64_t)lidar_pitch * p.height ||

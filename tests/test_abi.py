@@ -90,6 +90,15 @@ def test_validation(field, value, status):
     assert ei.value.status == status
 
 
+def test_cost_volume_offset_limit():
+    # one frame's cost volume is addressed with 32-bit byte offsets
+    assert sldf.workspace_size(sldf.default_params(width=4096, height=4096, max_disp=128,
+                                                   batch=1)) > 0
+    with pytest.raises(sldf.SldfError) as ei:
+        sldf.workspace_size(sldf.default_params(width=4096, height=4096, max_disp=256))
+    assert ei.value.status == sldf.ESHAPE
+
+
 def test_learned_check_needs_full_check_mode():
     for mode in (0, 1, 2):
         with pytest.raises(sldf.SldfError) as ei:
