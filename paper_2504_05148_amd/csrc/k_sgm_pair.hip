@@ -19,11 +19,12 @@
 
 namespace sldf {
 
-constexpr int kSeg = 4;   // checkpoint interval (pixels per segment)
+constexpr int kSeg = 8;   // checkpoint interval (pixels per segment)
+constexpr int kRing = 4;  // depth of the census / prior prefetch ring
 
 template <int G, int MODE, int VIEW>
-__device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, int line,
-                                         int g, int frame, int fv)
+__device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, u32x4* cw,
+                                         int line, int g, int frame, int fv)
 {
     constexpr int D = G * 8;
     constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
@@ -52,11 +53,11 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     auto ckpt = [&](int q) { return reinterpret_cast<u32x4*>(ck + (size_t)q * G * 4); };
 
     // ---- 1. forward direction r over segments 0 .. nseg-2, checkpoints ----
-    // R[j] holds the inputs of position kSeg q + j; each is reloaded for the
-    // next segment as soon as it has been used.
-    StepIn R[kSeg];
+    // R[j % kRing] holds the inputs of position u = kSeg q + j; each slot is
+    // reloaded with position u + kRing as soon as it has been used.
+    StepIn R[kRing];
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j) load(R[j], j);
+    for (int j = 0; j < kRing; ++j) load(R[j], j);
     {
         uint32_t L[4] = {0, 0, 0, 0};
         uint32_t m = 0;
@@ -64,8 +65,8 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
                 uint32_t C[4];
-                cost(R[j], q * kSeg + j, C);
-                load(R[j], (q + 1) * kSeg + j);
+                cost(R[j % kRing], q * kSeg + j, C);
+                load(R[j % kRing], q * kSeg + j + kRing);
                 rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast);
             }
             *ckpt(q) = u32x4{L[0], L[1], L[2], L[3]};
@@ -100,18 +101,26 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
         __builtin_amdgcn_sched_barrier(0);
         uint32_t Lf[4] = {Ln[0], Ln[1], Ln[2], Ln[3]};
         uint32_t mf = mn;
-        uint32_t Cb[kSeg][4], Lbuf[kSeg][4];
+        // the joint costs of the segment go to this lane's slots in LDS
+        // (cw[j * 64]), the forward states stay in registers
+        uint32_t Lbuf[kSeg][4];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) {
-            cost(R[j], u0 + j, Cb[j]);
-            load(R[j], u0 - kSeg + j);
-            rec8<G>(Lf, mf, Cb[j], p1x2, p2x2, gfirst, glast);
+            uint32_t C[4];
+            cost(R[j % kRing], u0 + j, C);
+            // the first kRing slots move on to the rest of this segment, the
+            // others to the start of segment s - 1
+            load(R[j % kRing], j < kRing ? u0 + j + kRing : u0 - kSeg + j - kRing);
+            cw[j * 64] = u32x4{C[0], C[1], C[2], C[3]};
+            rec8<G>(Lf, mf, C, p1x2, p2x2, gfirst, glast);
 #pragma unroll
             for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
         }
 #pragma unroll
         for (int j = kSeg - 1; j >= 0; --j) {
-            rec8<G>(Lb, mb, Cb[j], p1x2, p2x2, gfirst, glast);
+            const u32x4 cv = cw[j * 64];
+            const uint32_t C[4] = {cv.x, cv.y, cv.z, cv.w};
+            rec8<G>(Lb, mb, C, p1x2, p2x2, gfirst, glast);
             uint32_t St[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);
@@ -142,6 +151,7 @@ __global__ __launch_bounds__(256) void sgm_pair_kernel(SgmArgs a)
 {
     constexpr int D = G * 8;
     __shared__ uint32_t pat[2 * (D + 8) + 4];
+    __shared__ u32x4 cbuf[256 / 64][kSeg][64];   // per wave: segment costs
     build_pattern<D>(a, pat);
     __syncthreads();
     // XCD-aware mapping (blocks are dispatched round-robin over the XCDs):
@@ -158,9 +168,11 @@ __global__ __launch_bounds__(256) void sgm_pair_kernel(SgmArgs a)
     const int line = (logical - fv * a.blocks_per_fv) * (256 / G) + threadIdx.x / G;
     if (line >= a.nlines) return;
     if (view == 0)
-        run_pair<G, MODE, 0>(a, pat, line, g, frame, fv);
+        run_pair<G, MODE, 0>(a, pat, &cbuf[threadIdx.x / 64][0][threadIdx.x % 64], line, g,
+                             frame, fv);
     else
-        run_pair<G, MODE, 1>(a, pat, line, g, frame, fv);
+        run_pair<G, MODE, 1>(a, pat, &cbuf[threadIdx.x / 64][0][threadIdx.x % 64], line, g,
+                             frame, fv);
 }
 
 template <int G>

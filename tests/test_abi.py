@@ -53,9 +53,9 @@ def test_workspace_size_plan():
     census = 2 * (W + 2 * D) * H * 4            # padded census rows, both views
     # prior, d*, d' (i16), dsub (f32), S left + right (u16), LiDAR row masks
     # (D/32 words), rho (u16), cost features (2 u32), surrogate inputs (8 bf16)
-    # paired-direction checkpoints: every 4 pixels of each line, D u16 per
+    # paired-direction checkpoints: every 8 pixels of each line, D u16 per
     # checkpoint, both views; the largest pair is the diagonal one
-    segs = lambda n: (n + 3) // 4
+    segs = lambda n: (n + 7) // 8
     ck = max(H * segs(W), W * segs(H), (W + H - 1) * segs(min(W, H))) * D * 2 * 2
     exact = (census + px * (2 + 2 + 2 + 4) + 2 * cells * 2 + ck +
              px * (D // 32 * 4 + 2 + 8 + 16))
