@@ -32,18 +32,39 @@ PEAK_OPS32 = 256 * 64 * 2.4e9
 PEAK_OPS16 = 2 * PEAK_OPS32
 
 
-def sgm_ops_per_launch(frames: int, views: int, directions: int = 2):
-    """Algorithmic integer ops of one SGM launch: `directions` path
-    directions (a launch runs a direction and its opposite), both views, all
-    frames.  Per cell (pixel x disparity) and direction: the Eq. 2 step is 9
-    ops (two +P1, three mins, -m, +C, running min, +S) on 16-bit data; the
-    joint cost is xor + popcount (32-bit) plus the (1-alpha) scaling and, in
-    the left view, the DDC add (16-bit).  Work the kernel adds on top of the
-    method (the recomputed forward states of the pair scheme) is not
-    counted."""
+# Algorithmic integer work per cell (pixel x disparity), by peak class:
+# the Eq. 2 step is 9 ops per path (two +P1, three mins, -m, +C, running
+# min, +S) on u16 data (packed-16 peak); the joint cost is ~6 ops per cell in
+# the left view (xor, popcount, (1-alpha) scale, DDC select and add) and 3 in
+# the right view (xor, popcount, scale), computed once per cell whatever the
+# number of paths; the WTA is 2 ops per cell and view.  Cost, WTA and the
+# per-pixel steps count against the 32-bit peak.
+REC_OPS, COST_L, COST_R, WTA_OPS = 9, 6, 3, 2
+NUM_PATHS = 8
+
+
+def sgm_ops_per_launch(frames: int, views: int = 2):
+    """Algorithmic ops of one SGM launch, averaged over the num_paths / 2
+    launches of a frame: each launch runs two of the paths for every view;
+    the cost and the WTA are shared out evenly over the launches.  Work the
+    fused kernels add on top of the method (the cost recomputed per path, the
+    forward states recomputed by the pair scheme) is not counted."""
     cells = frames * W * H * D
-    ops32 = 2 * cells * views * directions
-    ops16 = (cells * (9 + 2) + (views - 1) * cells * (9 + 1)) * directions
+    launches = NUM_PATHS // 2
+    ops16 = cells * REC_OPS * 2 * views
+    ops32 = cells * ((COST_L + (views - 1) * COST_R) + WTA_OPS * views) / launches
+    return ops16, ops32
+
+
+def pipeline_ops_per_frame():
+    """Algorithmic ops of the whole plain path for one frame, by peak class:
+    recurrence (u16) for all paths and both views; cost, WTA, census (one
+    compare per bit and pixel, both views), semidensification (~200 per
+    pixel) and the bitset LiDAR window check (~100 per pixel) at 32 bits."""
+    n = W * H
+    cells = n * D
+    ops16 = cells * REC_OPS * NUM_PATHS * 2
+    ops32 = cells * (COST_L + COST_R + 2 * WTA_OPS) + n * (2 * 31 + 200 + 100)
     return ops16, ops32
 
 
@@ -90,10 +111,10 @@ def cpu_baseline(n_frames: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=125)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16, help="frames per step")
-    ap.add_argument("--latency-runs", type=int, default=200)
+    ap.add_argument("--latency-runs", type=int, default=1000)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
@@ -173,10 +194,21 @@ def main():
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
                     unit="Tops/s", frac=round(achieved / peak, 4), traffic=traffic,
                     kernel="sgm_pair_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
-                    ops_per_launch=int(ops16 + ops32))
+                    ops_per_launch=int(ops16 + ops32),
+                    peak_basis="u16 recurrence at the packed-16 peak, the rest at the "
+                               "32-bit peak",
+                    frac_int32=round(achieved / PEAK_OPS32, 4))
     if traffic:
         bw = traffic / avg_launch_s
         roofline.update(hbm_tb_s=round(bw / 1e12, 3), hbm_frac=round(bw / HBM_PEAK, 4))
+    p16, p32 = pipeline_ops_per_frame()
+    floor_cw = p16 / PEAK_OPS16 + p32 / PEAK_OPS32
+    floor_32 = (p16 + p32) / PEAK_OPS32
+    pipeline = dict(ops_per_frame=int(p16 + p32),
+                    floor_fps_class_weighted=round(1 / floor_cw, 1),
+                    floor_fps_int32=round(1 / floor_32, 1),
+                    frac_class_weighted=round(fps * floor_cw, 4),
+                    frac_int32=round(fps * floor_32, 4))
     stage_ms = {k: round(v[0] / (K * B), 4) for k, v in stages.items()}
     stream = torch.cuda.current_stream()
 
@@ -251,7 +283,8 @@ def main():
                            frames_per_step=B, width=W, height=H, max_disp=D,
                            check="plain", parallelism="single GPU, batched frames"),
                latency_ms=lat_plain,
-               stage_ms_per_frame=stage_ms, roofline=roofline, learned_check=learned)
+               stage_ms_per_frame=stage_ms, roofline=roofline, pipeline_floor=pipeline,
+               learned_check=learned)
     if args.serving_seconds > 0:
         # serving: six rigs (640x480 D=64, 1242x375 D=128, 1920x1080 D=256),
         # Poisson arrivals at 300 frames/s in total, continuous batching
