@@ -35,8 +35,11 @@ def test_budget_too_small_for_a_rig_never_allocates():
         pass
     # rig 1 can never get a slot: stop after a short while by running rig 0 only
     fin = srv.run([a for a in arr if a[1] == 0], realtime=True, progress=prog)
-    assert len(fin) == 2 and srv.peak_bytes == 10
+    # rig 0 may hold one or two slots (the second request can arrive while
+    # the first launch still runs); a rig-1 slot would exceed the budget
+    assert len(fin) == 2 and srv.peak_bytes in (10, 20)
     assert srv._get_slot(1) is None
+    assert srv.peak_bytes <= 50
 
 
 def test_failed_launches_release_resources():
