@@ -38,45 +38,119 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c)
 
 // ---------------------------------------------------------------------------
 // 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out.
-// Block: 4 waves, 64 x 4 pixels; wave w takes row y0 + w, four 16-px tiles.
+// A block computes 64 pixels of 4 output rows that lie on one dilation
+// lattice (rows y, y + d, y + 2d, y + 3d; wave w takes row w, four 16-px
+// tiles).  Those rows read the 6 input rows y - d .. y + 4d, columns
+// x0 - d .. x0 + 63 + d: they are staged once in LDS (zero outside the
+// image), so the nine taps of every output pixel read LDS instead of
+// fetching each input pixel nine times from the caches.  Blocks go to the
+// XCDs in contiguous ranges, so neighbouring column tiles share the halo
+// through one L2.
 // ---------------------------------------------------------------------------
+constexpr int kConvTileW = 64;
+constexpr int kConvRows = 4;
+constexpr int kConvMaxLds = 65536;
+constexpr int kConvMaxDil = 29;      // largest dilation whose tile fits the LDS budget
+
+// 16-byte chunk c of pixel q (CIN = 32: 4 chunks) is stored at chunk
+// position c ^ ((q >> 2) & 3): the 16 lanes of one LDS read pass (16
+// consecutive q, same c) then cover all 64 banks.
+template <int C16>
+__device__ __forceinline__ int swz(int q, int c)
+{
+    return C16 == 4 ? q * 4 + (c ^ ((q >> 2) & 3)) : q * C16 + c;
+}
+
 template <int CIN, int NMT>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntx, int qblocks,
+                                                      int nframes)
 {
     constexpr int OC = NMT * 16;                 // padded output channels
     constexpr int KSTEPS = CIN == 32 ? 9 : 3;
-    __shared__ __align__(16) uint16_t wl[9 * OC * CIN];
-    for (int i = threadIdx.x; i < 9 * OC * CIN / 8; i += 256)
-        reinterpret_cast<uint4*>(wl)[i] = reinterpret_cast<const uint4*>(a.w)[i];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4;
-    const int frame = blockIdx.z, y = blockIdx.y * 4 + wave;
-    if (y >= a.H) return;
+    constexpr int C16 = CIN / 8;                 // 16-byte chunks per pixel
+    constexpr int PPASS = 256 / C16;             // pixels staged per pass
+    constexpr int PASSES = (kConvTileW + 2 * kConvMaxDil + PPASS - 1) / PPASS;
+    extern __shared__ uint4 xin[];               // [kConvRows + 2][tw][C16], swizzled
+    const int d = a.dil;
+    const int tw = kConvTileW + 2 * d;
+    // block -> (frame, lattice residue r, lattice block qb, column tile tx)
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int logical = (b % 8) * (nb / 8) + b / 8;
+    const int per_frame = ntx * d * qblocks;
+    const int frame = logical / per_frame;
+    if (frame >= nframes) return;
+    int rem = logical - frame * per_frame;
+    const int yb = rem / ntx, tx = rem - yb * ntx;
+    const int r = yb / qblocks, qb = yb - r * qblocks;
+    const int x0 = tx * kConvTileW;
     const uint16_t* x = a.x + (int64_t)frame * a.px_stride * CIN;
-    for (int xt = 0; xt < 4; ++xt) {
-        const int px = blockIdx.x * 64 + xt * 16 + j;
-        f32x4 acc[NMT];
+
+    // stage the input tile: all loads are issued before the LDS writes
+    // (clamped addresses, zero where outside the image)
+    {
+        const int c = threadIdx.x % C16, pxo = threadIdx.x / C16;
+        uint4 v[kConvRows + 2][PASSES];
 #pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int row = 0; row < kConvRows + 2; ++row) {
+            const int sy = r + d * (kConvRows * qb + row - 1);
+            const int syc = min(max(sy, 0), a.H - 1);
 #pragma unroll
-        for (int ks = 0; ks < KSTEPS; ++ks) {
-            const int tap = CIN == 32 ? ks : 4 * ks + g;
-            const int ch0 = CIN == 32 ? 8 * g : 0;
-            uint4 bv = make_uint4(0, 0, 0, 0);
-            if (tap < 9) {
-                const int sx = px + (tap % 3 - 1) * a.dil, sy = y + (tap / 3 - 1) * a.dil;
-                if (px < a.W && sx >= 0 && sx < a.W && sy >= 0 && sy < a.H)
-                    bv = *reinterpret_cast<const uint4*>(x + ((int64_t)sy * a.W + sx) * CIN + ch0);
-            }
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) {
-                uint4 av = make_uint4(0, 0, 0, 0);
-                if (tap < 9)
-                    av = *reinterpret_cast<const uint4*>(wl + (tap * OC + 16 * mt + j) * CIN + ch0);
-                acc[mt] = mfma16(av, bv, acc[mt]);
+            for (int ps = 0; ps < PASSES; ++ps) {
+                const int sx = x0 - d + ps * PPASS + pxo;
+                const int sxc = min(max(sx, 0), a.W - 1);
+                v[row][ps] = *reinterpret_cast<const uint4*>(
+                    x + ((int64_t)syc * a.W + sxc) * CIN + 8 * c);
             }
         }
+#pragma unroll
+        for (int row = 0; row < kConvRows + 2; ++row) {
+            const int sy = r + d * (kConvRows * qb + row - 1);
+#pragma unroll
+            for (int ps = 0; ps < PASSES; ++ps) {
+                const int px = ps * PPASS + pxo;
+                const int sx = x0 - d + px;
+                const bool in = sy >= 0 && sy < a.H && sx >= 0 && sx < a.W;
+                if (px < tw) xin[swz<C16>(row * tw + px, c)] = in ? v[row][ps] : make_uint4(0, 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const int y = r + d * (kConvRows * qb + wave);
+    if (y >= a.H) return;
+    // the four 16-pixel tiles of the wave share each tap's weights (A
+    // operand, read from the cached weight array); every accumulator sums the
+    // taps in order
+    f32x4 acc[4][NMT];
+#pragma unroll
+    for (int xt = 0; xt < 4; ++xt)
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) acc[xt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int tap = CIN == 32 ? ks : 4 * ks + g;
+        const int ch0 = CIN == 32 ? 8 * g : 0;
+        uint4 av[NMT];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt)
+            av[mt] = tap < 9 ? *reinterpret_cast<const uint4*>(a.w + (tap * OC + 16 * mt + j) * CIN + ch0)
+                             : make_uint4(0, 0, 0, 0);
+        const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+        for (int xt = 0; xt < 4; ++xt) {
+            uint4 bv = make_uint4(0, 0, 0, 0);
+            if (tap < 9)
+                bv = xin[swz<C16>((wave + ky) * tw + xt * 16 + j + kx * d, CIN == 32 ? g : 0)];
+#pragma unroll
+            for (int mt = 0; mt < NMT; ++mt) acc[xt][mt] = mfma16(av[mt], bv, acc[xt][mt]);
+        }
+    }
+#pragma unroll
+    for (int xt = 0; xt < 4; ++xt) {
+        const int px = x0 + xt * 16 + j;
         if (px >= a.W) continue;
         const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
         // lane holds pixel j, output channels 16 mt + 4 g + e
@@ -86,7 +160,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
             float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                v[e] = acc[mt][e] + (a.bias && oc0 + e < a.cout ? a.bias[oc0 + e] : 0.f);
+                v[e] = acc[xt][mt][e] + (a.bias && oc0 + e < a.cout ? a.bias[oc0 + e] : 0.f);
                 if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
             }
             if (a.gate) {
@@ -108,14 +182,28 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
     }
 }
 
+template <int CIN, int NMT>
+static hipError_t launch_conv_t(const ConvArgs& a, int nframes, hipStream_t s)
+{
+    const int d = a.dil;
+    const size_t lds = (size_t)(kConvRows + 2) * (kConvTileW + 2 * d) * CIN * 2;
+    if (d < 1 || d > kConvMaxDil || lds > (size_t)kConvMaxLds) return hipErrorInvalidValue;
+    const int ntx = (a.W + kConvTileW - 1) / kConvTileW;
+    const int lattice_rows = (a.H + d - 1) / d;                  // rows per residue, at most
+    const int qblocks = (lattice_rows + kConvRows - 1) / kConvRows;
+    const int64_t nb = (int64_t)ntx * d * qblocks * nframes;
+    dim3 grid((unsigned)((nb + 7) / 8 * 8));
+    hipLaunchKernelGGL((conv3x3_kernel<CIN, NMT>), grid, dim3(256), lds, s, a, ntx, qblocks,
+                       nframes);
+    return hipGetLastError();
+}
+
 hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hipStream_t s)
 {
-    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, nframes);
-    if (cin == 32 && cout_pad == 32) hipLaunchKernelGGL((conv3x3_kernel<32, 2>), grid, dim3(256), 0, s, a);
-    else if (cin == 8 && cout_pad == 32) hipLaunchKernelGGL((conv3x3_kernel<8, 2>), grid, dim3(256), 0, s, a);
-    else if (cin == 32 && cout_pad == 16) hipLaunchKernelGGL((conv3x3_kernel<32, 1>), grid, dim3(256), 0, s, a);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (cin == 32 && cout_pad == 32) return launch_conv_t<32, 2>(a, nframes, s);
+    if (cin == 8 && cout_pad == 32) return launch_conv_t<8, 2>(a, nframes, s);
+    if (cin == 32 && cout_pad == 16) return launch_conv_t<32, 1>(a, nframes, s);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
