@@ -43,16 +43,15 @@ REC_OPS, COST_L, COST_R, WTA_OPS = 9, 6, 3, 2
 NUM_PATHS = 8
 
 
-def sgm_ops_per_launch(frames: int, views: int = 2):
-    """Algorithmic ops of one SGM launch, averaged over the num_paths / 2
-    launches of a frame: each launch runs two of the paths for every view;
-    the cost and the WTA are shared out evenly over the launches.  Work the
-    fused kernels add on top of the method (the cost recomputed per path, the
-    forward states recomputed by the pair scheme) is not counted."""
+def sgm_ops_per_step(frames: int, views: int = 2):
+    """Algorithmic ops of the SGM passes over one step (all paths of every
+    frame and view): the recurrence per path and view, the cost and the WTA
+    once per cell.  Work the fused kernels add on top of the method (the
+    cost recomputed per path, the forward states recomputed by the pair
+    scheme) is not counted."""
     cells = frames * W * H * D
-    launches = NUM_PATHS // 2
-    ops16 = cells * REC_OPS * 2 * views
-    ops32 = cells * ((COST_L + (views - 1) * COST_R) + WTA_OPS * views) / launches
+    ops16 = cells * REC_OPS * NUM_PATHS * views
+    ops32 = cells * ((COST_L + (views - 1) * COST_R) + WTA_OPS * views)
     return ops16, ops32
 
 
@@ -186,7 +185,9 @@ def main():
     # roofline of the dominant kernel: the SGM path pass
     sgm_ms, sgm_launches = stages["sgm"]
     avg_launch_s = sgm_ms / 1e3 / max(sgm_launches, 1)
-    ops16, ops32 = sgm_ops_per_launch(B, 2)
+    launches_per_step = max(sgm_launches, 1) / K
+    s16, s32 = sgm_ops_per_step(B, 2)
+    ops16, ops32 = s16 / launches_per_step, s32 / launches_per_step   # per launch, averaged
     floor_s = ops16 / PEAK_OPS16 + ops32 / PEAK_OPS32
     peak = (ops16 + ops32) / floor_s
     achieved = (ops16 + ops32) / avg_launch_s
