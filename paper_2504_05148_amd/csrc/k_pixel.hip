@@ -112,41 +112,71 @@ hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s)
 // sparse disparities in the (2 rs + 1)^2 window (clipped), take the one with
 // the smallest Hamming cost H(p, d) (ties -> smallest d); keep it if that
 // cost is below Ts, otherwise keep the sparse value of p.
-// Block: 16 x 16 pixels; the LiDAR window tile is staged in LDS.
+// Block: 16 x 16 pixels.  The LiDAR window tile is staged in LDS and its
+// valid points are compacted into a list (the map is sparse, so a pixel
+// visits a few dozen points instead of every window tap); the right-view
+// census of the columns a match can reach (x0 - D + 1 .. x0 + 15) is staged
+// too.  The minimum over (H, d) does not depend on the visiting order.
 // ---------------------------------------------------------------------------
-constexpr int kSemiT = 16, kSemiMaxR = 15, kSemiLT = kSemiT + 2 * kSemiMaxR;
+constexpr int kSemiT = 16, kSemiMaxR = 15, kSemiLT = kSemiT + 2 * kSemiMaxR, kSemiMaxD = 256;
 
 __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
 {
     __shared__ int16_t tile[kSemiLT][kSemiLT];
+    __shared__ uint32_t cand[kSemiLT * kSemiLT];          // (row << 16) | (col << 8) | d
+    __shared__ uint32_t crow[kSemiT][kSemiMaxD + kSemiT];  // right census of the reachable columns
+    __shared__ int ncand;
     const int frame = blockIdx.z;
     const int16_t* lid = a.lidar + (int64_t)frame * a.lidar_fstride;
-    const int rs = a.rs, lt = kSemiT + 2 * rs;
+    const int rs = a.rs, lt = kSemiT + 2 * rs, D = a.D;
     const int x0 = blockIdx.x * kSemiT, y0 = blockIdx.y * kSemiT;
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
     for (int i = threadIdx.x; i < lt * lt; i += 256) {
         int r = i / lt, c = i - r * lt;
         int gy = y0 - rs + r, gx = x0 - rs + c;
         int16_t v = -1;
         if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = lid[(int64_t)gy * a.lidar_pitch + gx];
         tile[r][c] = v;
+        // values outside [0, D) are no candidates (the ABI admits only -1)
+        if ((unsigned)v < (unsigned)D) cand[atomicAdd(&ncand, 1)] = (r << 16) | (c << 8) | v;
+    }
+    // census rows are padded by D codes on each side: columns down to -D are
+    // inside the buffer
+    const uint32_t* crb = a.census_r + (int64_t)frame * a.census_fstride;
+    const int cw = D + kSemiT - 1;
+    for (int i = threadIdx.x; i < kSemiT * cw; i += 256) {
+        const int r = i / cw, k = i - r * cw, gy = y0 + r;
+        crow[r][k] = gy < a.H ? crb[(int64_t)gy * a.census_pitch + x0 - D + 1 + k] : 0u;
     }
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int x = x0 + tx, y = y0 + ty;
     if (x >= a.W || y >= a.H) return;
-    const uint32_t* cl = a.census_l + (int64_t)frame * a.census_fstride;
-    const uint32_t* cr_row = a.census_r + (int64_t)frame * a.census_fstride + (int64_t)y * a.census_pitch;
-    const uint32_t c = cl[(int64_t)y * a.census_pitch + x];
+    const uint32_t c = a.census_l[(int64_t)frame * a.census_fstride + (int64_t)y * a.census_pitch + x];
     uint32_t best = 0xffffffffu;   // (H << 16) | d, lexicographic minimum
-    for (int r = 0; r <= 2 * rs; ++r) {
-        for (int q = 0; q <= 2 * rs; ++q) {
-            int d = tile[ty + r][tx + q];
-            if (d < 0) continue;
-            int xm = x - d;
-            uint32_t h = xm >= 0 ? (uint32_t)__builtin_popcount(c ^ cr_row[xm]) : (uint32_t)a.n;
-            uint32_t key = (h << 16) | (uint32_t)d;
-            best = key < best ? key : best;
+    auto visit = [&](int d) {
+        // matching pixel x - d: staged column tx - d + D - 1 (in [0, cw) for
+        // 0 <= d < D)
+        const uint32_t h = x - d >= 0 ? (uint32_t)__builtin_popcount(c ^ crow[ty][tx - d + D - 1])
+                                      : (uint32_t)a.n;
+        const uint32_t key = (h << 16) | (uint32_t)d;
+        best = key < best ? key : best;
+    };
+    const int n = ncand, w = 2 * rs + 1;
+    if (n < w * w) {
+        for (int k = 0; k < n; ++k) {
+            const uint32_t e = cand[k];
+            const int r = (int)(e >> 16), cc = (int)((e >> 8) & 0xff);
+            if ((unsigned)(r - ty) < (unsigned)w && (unsigned)(cc - tx) < (unsigned)w)
+                visit((int)(e & 0xff));
         }
+    } else {
+        for (int r = 0; r < w; ++r)
+            for (int q = 0; q < w; ++q) {
+                const int d = tile[ty + r][tx + q];
+                if ((unsigned)d < (unsigned)D) visit(d);
+            }
     }
     int16_t outv = lid[(int64_t)y * a.lidar_pitch + x];
     if ((best >> 16) < (uint32_t)a.ts) outv = (int16_t)(best & 0xffffu);

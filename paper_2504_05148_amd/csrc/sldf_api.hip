@@ -399,6 +399,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         sa.px_stride = b.px_stride;
         sa.W = W;
         sa.H = H;
+        sa.D = D;
         sa.n = ctx->n;
         sa.ts = p.ts;
         sa.rs = p.rs;

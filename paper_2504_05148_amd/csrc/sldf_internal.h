@@ -57,7 +57,7 @@ struct SemiArgs {
     int64_t lidar_fstride;
     int16_t* out;
     int64_t px_stride;
-    int32_t W, H, n, ts, rs;
+    int32_t W, H, D, n, ts, rs;
 };
 
 struct SgmArgs {
