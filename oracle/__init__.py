@@ -78,13 +78,15 @@ class OracleParams:
     rc: int = 20
     check_mode: int = 3
     subpixel: int = 1
+    prior_cost: int = 0
+    huber_k: int = 1
 
 
 class _CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int) for k in (
         "W", "H", "D", "cw", "ch", "num_paths", "p1", "p2", "q1", "q2", "a", "b",
         "blend_mode", "semidense", "ts", "rs", "tc", "rc", "check_mode",
-        "subpixel")]
+        "subpixel", "prior_cost", "huber_k")]
 
 
 def _chk(rc):
@@ -123,7 +125,14 @@ def semidense(cL, cR, lidar, n, ts, rs) -> np.ndarray:
     return out
 
 
-def joint_cost(cL, cR, prior, D, n, view, a, b, q1, q2, blend_mode=0):
+def prior_penalty(adiff, q1, q2, prior_cost=0, huber_k=1) -> int:
+    """Penalty q of a disparity |d - prior| = adiff away from the prior."""
+    return int(_load().orc_prior_penalty(int(adiff), int(q1), int(q2), int(prior_cost),
+                                         int(huber_k)))
+
+
+def joint_cost(cL, cR, prior, D, n, view, a, b, q1, q2, blend_mode=0, prior_cost=0,
+               huber_k=1):
     """C'(p,d) as int32 [H, W, D]; prior None means no prior anywhere."""
     cL = np.ascontiguousarray(cL, np.uint32)
     cR = np.ascontiguousarray(cR, np.uint32)
@@ -134,7 +143,8 @@ def joint_cost(cL, cR, prior, D, n, view, a, b, q1, q2, blend_mode=0):
         pr = np.ascontiguousarray(prior, np.int16)
     _chk(_load().orc_joint_cost(_p(cL, u32), _p(cR, u32),
                                 _p(pr, i16) if pr is not None else None, W, H, D, n,
-                                view, a, b, q1, q2, blend_mode, _p(out, i32)))
+                                view, a, b, q1, q2, blend_mode, prior_cost, huber_k,
+                                _p(out, i32)))
     return out
 
 

@@ -159,16 +159,40 @@ int orc_semidense(const uint32_t* cL, const uint32_t* cR, const int16_t* lidar,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Penalty of a disparity that is adiff = |d - prior| away from the prior.   */
+/* prior_cost 0: the DDC of Eq. 4 (Sec. IV-A): 0, Q1 at distance 1, Q2       */
+/* beyond.  The other two are the LiDAR cost terms the paper compares DDC    */
+/* with (Sec. IV-A, Sec. V-B), in the reading used here, capped at Q2 so     */
+/* that the 16-bit bound of the DDC still holds:                             */
+/*   1: quadratic (the LiDAR-SGM term): min(Q1 adiff^2, Q2);                 */
+/*   2: Huber with threshold k: twice the Huber function, adiff^2 up to k,   */
+/*      k (2 adiff - k) beyond, times Q1, capped at Q2.                      */
+/* ------------------------------------------------------------------------ */
+int orc_prior_penalty(int adiff, int q1, int q2, int prior_cost, int huber_k)
+{
+    long long r;
+    if (prior_cost == 0) return adiff == 0 ? 0 : (adiff == 1 ? q1 : q2);
+    if (prior_cost == 1 || adiff <= huber_k)
+        r = (long long)adiff * adiff;
+    else
+        r = (long long)huber_k * (2LL * adiff - huber_k);
+    r *= q1;
+    return r < q2 ? (int)r : q2;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Joint matching cost, Eq. 4 (Sec. IV-A), scaled by b:                     */
-/*   C'(p,d) = (b - a) H(p,d) + a * DDC(d, prior_p)                          */
-/*   DDC = 0 if d == prior, Q1 if |d - prior| == 1, Q2 otherwise.           */
+/*   C'(p,d) = (b - a) H(p,d) + a * q(|d - prior_p|)                         */
+/* with q the DDC (0 if d == prior, Q1 if |d - prior| == 1, Q2 otherwise)   */
+/* or one of the alternative terms of orc_prior_penalty.                    */
 /* prior may be NULL (no prior anywhere, as in the right-view pass).        */
 /* view 0: left image is base; view 1: right image is base.                 */
 /* Output layout: cost[(y * W + x) * D + d].                                */
 /* ------------------------------------------------------------------------ */
 int orc_joint_cost(const uint32_t* cL, const uint32_t* cR, const int16_t* prior,
                    int W, int H, int D, int n, int view, int a, int b, int q1,
-                   int q2, int blend_mode, int32_t* cost)
+                   int q2, int blend_mode, int prior_cost, int huber_k,
+                   int32_t* cost)
 {
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {
@@ -183,7 +207,7 @@ int orc_joint_cost(const uint32_t* cL, const uint32_t* cR, const int16_t* prior,
                 } else {
                     int diff = d - e;
                     if (diff < 0) diff = -diff;
-                    int q = diff == 0 ? 0 : (diff == 1 ? q1 : q2);
+                    int q = orc_prior_penalty(diff, q1, q2, prior_cost, huber_k);
                     c = (b - a) * h + a * q;
                 }
                 cost[((size_t)y * W + x) * D + d] = c;
@@ -429,6 +453,8 @@ typedef struct {
     int ts, rs, tc, rc;
     int check_mode;
     int subpixel;
+    int prior_cost;     /* 0 DDC, 1 quadratic, 2 Huber (orc_prior_penalty) */
+    int huber_k;
 } orc_params;
 
 int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
@@ -460,7 +486,7 @@ int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
     else
         memcpy(prior, lidar, px * 2);
     orc_joint_cost(cL, cR, prior, W, H, D, n, 0, P->a, P->b, P->q1, P->q2,
-                   P->blend_mode, cost);
+                   P->blend_mode, P->prior_cost, P->huber_k, cost);
     if ((st = orc_aggregate(cost, W, H, D, P->num_paths, P->b * P->p1,
                             P->b * P->p2, S)))
         goto done;
@@ -468,7 +494,7 @@ int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
     if (tap_S) memcpy(tap_S, S, cells * 4);
     if (P->check_mode == 1 || P->check_mode == 3) {
         orc_joint_cost(cL, cR, NULL, W, H, D, n, 1, P->a, P->b, P->q1, P->q2,
-                       P->blend_mode, cost);
+                       P->blend_mode, P->prior_cost, P->huber_k, cost);
         if ((st = orc_aggregate(cost, W, H, D, P->num_paths, P->b * P->p1,
                                 P->b * P->p2, S)))
             goto done;

@@ -94,6 +94,48 @@ def test_ddc_invariants():
     assert (c0 == b * hv).all()
 
 
+def test_alternative_prior_terms():
+    """The LiDAR cost terms DDC is compared with (quadratic, Huber; capped at
+    Q2), checked against what their definitions imply: a parabola has
+    constant second differences; Huber equals the parabola up to k and then
+    continues with the parabola's slope at k; Huber lies below the parabola;
+    a cap of Q1 reduces both to the DDC with Q1 = Q2."""
+    q1, big, D = 3, 10 ** 6, 256
+    quad = [oracle.prior_penalty(t, q1, big, 1) for t in range(D)]
+    assert quad[0] == 0
+    assert all(quad[t + 1] - 2 * quad[t] + quad[t - 1] == 2 * q1 for t in range(1, D - 1))
+    # Huber with k beyond the disparity range has no linear part
+    assert [oracle.prior_penalty(t, q1, big, 2, D) for t in range(D)] == quad
+    for k in (1, 3, 8):
+        hub = [oracle.prior_penalty(t, q1, big, 2, k) for t in range(D)]
+        assert hub[:k + 1] == quad[:k + 1]
+        # straight tail whose slope, 2 q1 k, is the parabola's derivative at k
+        assert all(hub[t + 1] - hub[t] == 2 * q1 * k for t in range(k, D - 1))
+        assert all(0 <= h <= qd for h, qd in zip(hub, quad))
+    for mode in (1, 2):
+        assert [oracle.prior_penalty(t, 7, 7, mode, 2) for t in range(D)] == \
+            [oracle.prior_penalty(t, 7, 7, 0) for t in range(D)]
+    capped = [oracle.prior_penalty(t, 5, 160, 1) for t in range(D)]
+    assert max(capped) == 160 and all(b >= a for a, b in zip(capped, capped[1:]))
+    assert capped[:6] == [0, 5, 20, 45, 80, 125]
+    # in the joint cost, mode 0 is the DDC of Eq. 4 unchanged
+    rng = np.random.default_rng(4)
+    W, H, Dd, n = 30, 6, 32, 12
+    cl = rng.integers(0, 1 << 12, size=(H, W)).astype(np.uint32)
+    cr = rng.integers(0, 1 << 12, size=(H, W)).astype(np.uint32)
+    prior = rng.integers(-1, Dd, size=(H, W)).astype(np.int16)
+    c0 = oracle.joint_cost(cl, cr, prior, Dd, n, 0, 7, 10, 5, 160)
+    c1 = oracle.joint_cost(cl, cr, prior, Dd, n, 0, 7, 10, 5, 160, prior_cost=0, huber_k=4)
+    assert (c0 == c1).all()
+    # with alpha = 1 the cost is the prior term alone: its minimum over d sits
+    # at the prior in every mode
+    for mode in (0, 1, 2):
+        c = oracle.joint_cost(cl, cr, prior, Dd, n, 0, 10, 10, 5, 160, prior_cost=mode,
+                              huber_k=2)
+        has = prior >= 0
+        assert (c.argmin(axis=2)[has] == prior[has]).all()
+
+
 # -------------------------------------------------------- path recurrence --
 def _line_pixels(W, H, dx, dy):
     """All maximal lines of direction (dx, dy), each in traversal order."""
