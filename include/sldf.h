@@ -104,6 +104,14 @@ typedef struct {
                               back to the plain check (decided on the device,
                               no host synchronisation); in [0, 1] */
     float uncertain_margin;  /* >= 0 */
+    int32_t prior_cost;    /* LiDAR term of the joint cost: 0 = DDC (Eq. 4,
+                              the paper's method); the terms it is compared
+                              with (Sec. IV-A, V-B), capped at q2 so that the
+                              16-bit bound holds: 1 = quadratic
+                              min(q1 t^2, q2), 2 = Huber min(q1 h_k(t), q2)
+                              with h_k(t) = t^2 (t <= k), k (2t - k) beyond;
+                              t = |d - prior| */
+    int32_t huber_k;       /* Huber threshold k >= 1 (prior_cost 2) */
 } sldf_params;
 
 /* Optional debug taps: device pointers, any may be NULL.  Written for frame

@@ -334,10 +334,12 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
     }
 }
 
-// DDC pattern table in LDS (the Eq. 4 term: 0 at the prior, Q1 at +-1, Q2
-// beyond) as pairs of u16 starting at even (first half) and odd (second
-// half) entries of P[k] = ddc(k - D), k in [0, 2D + 16), followed by a run of
-// zeros used where a pixel has no prior.
+// Prior-term table in LDS, P[k] = alpha_num * q(|k - D|), k in [0, 2D + 16):
+// the DDC of Eq. 4 (0 at the prior, Q1 at +-1, Q2 beyond) or, by
+// prior_cost, the quadratic min(Q1 t^2, Q2) or Huber min(Q1 h_k(t), Q2)
+// terms; stored as pairs of u16 starting at even (first half) and odd
+// (second half) entries, followed by a run of zeros used where a pixel has
+// no prior.
 template <int D>
 __device__ __forceinline__ void build_pattern(const SgmArgs& a, uint32_t* pat)
 {
@@ -350,7 +352,14 @@ __device__ __forceinline__ void build_pattern(const SgmArgs& a, uint32_t* pat)
             for (int j = 0; j < 2; ++j) {
                 int diff = k0 + j - D;
                 diff = diff < 0 ? -diff : diff;
-                v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+                if (a.prior_cost == 0) {
+                    v[j] = diff == 0 ? 0u : (diff == 1 ? a.q1s : a.q2s);
+                } else {
+                    const uint64_t t = (uint64_t)diff, k = (uint64_t)a.huber_k;
+                    const uint64_t r = (a.prior_cost == 1 || t <= k) ? t * t : k * (2 * t - k);
+                    const uint64_t q = r * a.q1s;   // num * Q1 * r, capped at num * Q2
+                    v[j] = q < a.q2s ? (uint32_t)q : a.q2s;
+                }
             }
         }
         pat[i] = v[0] | (v[1] << 16);

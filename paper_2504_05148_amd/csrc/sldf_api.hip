@@ -71,6 +71,8 @@ sldf_status validate(const sldf_params* p)
          !(p->uncertain_margin >= 0.f)))
         return SLDF_EINVAL;
     if (p->subpixel != 0 && p->subpixel != 1) return SLDF_EINVAL;
+    if (p->prior_cost < 0 || p->prior_cost > 2 || p->huber_k < 1 || p->huber_k > 4096)
+        return SLDF_EINVAL;
     if (p->batch < 1 || p->batch > 4096) return SLDF_EINVAL;
     // 16-bit bound: every L_r lies in [C', C' + P2'] (Eq. 2), the sum of the
     // paths in [|R| C', |R| (C' + P2')], and the largest intermediate of the
@@ -214,6 +216,8 @@ void sldf_params_default(sldf_params* p)
     p->batch = 1;
     p->fallback_tau = 0.05f;
     p->uncertain_margin = 0.5f;
+    p->prior_cost = 0;    // DDC
+    p->huber_k = 1;
 }
 
 sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes)
@@ -435,6 +439,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.n = ctx->n;
     ga.mulh_prior = (uint32_t)(p.alpha_den - p.alpha_num);
     ga.mulh_noprior = (uint32_t)(p.blend_mode ? p.alpha_den : p.alpha_den - p.alpha_num);
+    ga.prior_cost = p.prior_cost;
+    ga.huber_k = p.huber_k;
     ga.q1s = (uint32_t)(p.alpha_num * p.q1);
     ga.q2s = (uint32_t)(p.alpha_num * p.q2);
     ga.p1s = (uint32_t)(p.alpha_den * p.p1);

@@ -80,6 +80,8 @@ struct SgmArgs {
     uint32_t mulh_prior;        // (den - num)
     uint32_t mulh_noprior;      // (den - num) or den (blend mode 1)
     uint32_t q1s, q2s;          // num * Q1, num * Q2
+    int32_t prior_cost;         // 0 DDC, 1 quadratic, 2 Huber (table in build_pattern)
+    int32_t huber_k;
     uint32_t p1s, p2s;          // den * P1, den * P2
     int32_t subpixel;
     int32_t store_sum;          // last pass also stores S (debug tap)

@@ -25,14 +25,16 @@ _PARAM_FIELDS = ("struct_size", "width", "height", "max_disp", "census_w", "cens
 
 
 _PARAM_FLOATS = ("fallback_tau", "uncertain_margin")
+_PARAM_TAIL = ("prior_cost", "huber_k")     # int32 fields after the floats
 
 
 class Params(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int32) for k in _PARAM_FIELDS] +
-                [(k, ctypes.c_float) for k in _PARAM_FLOATS])
+                [(k, ctypes.c_float) for k in _PARAM_FLOATS] +
+                [(k, ctypes.c_int32) for k in _PARAM_TAIL])
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in _PARAM_FIELDS + _PARAM_FLOATS}
+        return {k: getattr(self, k) for k in _PARAM_FIELDS + _PARAM_FLOATS + _PARAM_TAIL}
 
 
 class Taps(ctypes.Structure):
@@ -111,7 +113,7 @@ def default_params(**overrides) -> Params:
     p = Params()
     lib().sldf_params_default(ctypes.byref(p))
     for k, v in overrides.items():
-        if k in _PARAM_FIELDS:
+        if k in _PARAM_FIELDS or k in _PARAM_TAIL:
             setattr(p, k, int(v))
         elif k in _PARAM_FLOATS:
             setattr(p, k, float(v))

@@ -42,6 +42,7 @@ def test_params_default_is_tab2():
     assert (p.width, p.height, p.max_disp, p.census_w, p.census_h, p.num_paths) == (
         1242, 375, 128, 9, 7, 8)
     assert p.semidense == 1 and p.check_mode == 3 and p.subpixel == 1
+    assert p.prior_cost == 0 and p.huber_k == 1            # DDC (Eq. 4)
     assert sldf.lib().sldf_abi_version() == 1
 
 
@@ -81,6 +82,8 @@ def test_workspace_size_plan():
     ("check_mode", 4, sldf.EINVAL),
     ("check_impl", 2, sldf.EINVAL),
     ("batch", 0, sldf.EINVAL),
+    ("prior_cost", 3, sldf.EINVAL),
+    ("huber_k", 0, sldf.EINVAL),
     ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
 ])
 def test_validation(field, value, status):

@@ -28,7 +28,8 @@ def _oracle_params(p: dict) -> oracle.OracleParams:
         a=p.get("alpha_num", 7), b=p.get("alpha_den", 10), blend_mode=p.get("blend_mode", 0),
         semidense=p.get("semidense", 1), ts=p.get("ts", 2), rs=p.get("rs", 6),
         tc=p.get("tc", 2), rc=p.get("rc", 20), check_mode=p.get("check_mode", 3),
-        subpixel=p.get("subpixel", 1))
+        subpixel=p.get("subpixel", 1), prior_cost=p.get("prior_cost", 0),
+        huber_k=p.get("huber_k", 1))
 
 
 def run_gpu(frame, pkw, taps=True):
@@ -136,6 +137,15 @@ def test_paper_scale_frame():
     assert (g["dsub"].view(np.uint32) == o["dsub"].view(np.uint32)).all()
 
 
+@pytest.mark.parametrize("prior_cost,huber_k", [(1, 1), (2, 2)])
+def test_paper_scale_alternative_prior_terms(prior_cost, huber_k):
+    """The quadratic and Huber LiDAR terms through the same aggregation."""
+    f = synth.kitti_frame(3)
+    pkw = _params(1242, 375, 128, prior_cost=prior_cost, huber_k=huber_k, q2=980)
+    print(f"case kitti prior_cost={prior_cost} k={huber_k}", flush=True)
+    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+
+
 def test_paper_scale_dsgm():
     f = synth.kitti_frame(1)
     pkw = _params(1242, 375, 128, semidense=0)
@@ -157,6 +167,8 @@ def test_ragged_shapes(W, H, D, paths):
     dict(blend_mode=1), dict(subpixel=0), dict(num_paths=1), dict(rs=0, rc=0, tc=0),
     dict(rs=15, rc=31, ts=9), dict(alpha_num=0), dict(alpha_num=10, q1=0, q2=5),
     dict(census_w=7, census_h=7), dict(census_w=3, census_h=9), dict(p1=0, p2=0),
+    dict(prior_cost=1), dict(prior_cost=1, q2=980), dict(prior_cost=2, huber_k=1),
+    dict(prior_cost=2, huber_k=3, q2=980),
 ])
 def test_parameter_variants(extra):
     f = synth.small_frame(4)
