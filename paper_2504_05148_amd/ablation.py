@@ -8,6 +8,8 @@ paper's studies, scored with coverage / covered error / total error
   stereo-LiDAR check of Eq. 6 (plus no check) on the SDSGM output;
 - method variants (Tab. I): SGM with census only (alpha = 0), DSGM, SDSGM,
   and SDSGM with the learned check;
+- LiDAR cost terms (Tab. III): the DDC against the quadratic (LiDAR-SGM)
+  and Huber terms, on the sparse and on the semidense prior;
 - parameter sweeps: any sldf_params field (T_s, r_s, Q1, Q2, T_c, r_c, ...)
   through --sweep name=v1,v2,...
 
@@ -100,6 +102,26 @@ def variants(frames, surrogate=None) -> dict:
     return out
 
 
+# the LiDAR cost terms DDC is compared with (Sec. IV-A, Tab. III), on the
+# raw sparse map (as LiDAR-SGM uses it) and on the semidense one; the cap
+# q2 = 980 is the largest the 16-bit bound admits at Tab. II otherwise
+PRIOR_TERMS = {
+    "DDC (Eq. 4)": dict(prior_cost=0),
+    "quadratic": dict(prior_cost=1, q2=980),
+    "Huber, k = 2": dict(prior_cost=2, huber_k=2, q2=980),
+}
+
+
+def prior_terms(frames) -> dict:
+    """Tab. III shape: DDC against the quadratic and Huber LiDAR terms."""
+    out = {}
+    for semi, tag in ((0, "D-bar"), (1, "D-hat")):
+        for name, kw in PRIOR_TERMS.items():
+            out[f"{name}, {tag}"] = evaluate.evaluate_frames(
+                run_frames(frames, semidense=semi, **kw), frames)
+    return out
+
+
 def sweep(frames, name: str, values) -> dict:
     return {f"{name}={v}": evaluate.evaluate_frames(run_frames(frames, **{name: v}), frames)
             for v in values}
@@ -135,6 +157,7 @@ def main(argv=None):
     print(table("Prior maps (Tab. IV shape)", prior_maps(frames)), "\n")
     print(table("Consistency checks on SDSGM (Tab. V shape)", check_modes(frames)), "\n")
     print(table("Method variants (Tab. I)", variants(frames, _load_surrogate())), "\n")
+    print(table("LiDAR cost terms (Tab. III shape)", prior_terms(frames)), "\n")
     for s in args.sweep:
         name, vals = s.split("=")
         print(table(f"Sweep of {name}", sweep(frames, name, [int(v) for v in vals.split(",")])),

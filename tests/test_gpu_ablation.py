@@ -44,3 +44,10 @@ def test_variants_and_table(frames):
         assert 0.0 <= e["covered_error"] <= 1.0 and 0.0 < e["coverage"] <= 1.0
     t = ablation.table("variants", rows)
     assert t.count("\n") == len(rows) + 3
+
+
+def test_prior_terms_rows(frames):
+    rows = ablation.prior_terms(frames[:1])
+    assert len(rows) == 2 * len(ablation.PRIOR_TERMS)
+    for e in rows.values():
+        assert 0.0 < e["coverage"] <= 1.0
