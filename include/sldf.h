@@ -158,7 +158,8 @@ void sldf_params_default(sldf_params* p);
 
 /* Validate p (shape ranges, odd census window, D, num_paths, q1 <= q2,
    alpha in [0, 1], the 16-bit bound
-     num_paths * (C'max + P2') < 65536 and C'max + P1' + 2 P2' < 65536,
+     num_paths * (C'max + P2') < 65536 and C'max + P2' + max(P1', P2') <
+     0x7c00 (the recurrence compares its terms as fp16 bit patterns),
    with C'max the largest joint cost) and return the exact device workspace
    size for p->batch frames in *bytes.  Host only.
    Errors: EINVAL, ESHAPE, EOVERFLOW. */

@@ -183,6 +183,39 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     a.out[(int64_t)frame * a.px_stride + (int64_t)y * a.W + x] = outv;
 }
 
+// The path passes read the prior as one 32-bit word per pixel: DSGM widens
+// the caller's D-bar map, the debug tap narrows it back.
+__global__ void widen_prior_kernel(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                                   int32_t* out, int32_t W, int32_t H, int64_t out_fstride)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, f = blockIdx.z;
+    if (x >= W) return;
+    out[(int64_t)f * out_fstride + (int64_t)y * W + x] =
+        in[(int64_t)f * in_fstride + (int64_t)y * in_pitch + x];
+}
+
+hipError_t launch_widen_prior(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                              int32_t* out, int32_t W, int32_t H, int64_t out_fstride,
+                              int nframes, hipStream_t s)
+{
+    hipLaunchKernelGGL(widen_prior_kernel, dim3((W + 255) / 256, H, nframes), dim3(256), 0, s,
+                       in, in_pitch, in_fstride, out, W, H, out_fstride);
+    return hipGetLastError();
+}
+
+__global__ void narrow_prior_kernel(const int32_t* in, int16_t* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = (int16_t)in[i];
+}
+
+hipError_t launch_narrow_prior(const int32_t* in, int16_t* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(narrow_prior_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       in, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s)
 {
     dim3 grid((a.W + kSemiT - 1) / kSemiT, (a.H + kSemiT - 1) / kSemiT, nframes);

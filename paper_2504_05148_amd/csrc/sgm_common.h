@@ -23,6 +23,19 @@ __device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
 }
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) { return u1(v2(a) + v2(b)); }
 __device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) { return u1(v2(a) - v2(b)); }
+// Three-way packed minimum of u16 values below 0x7c00: such bit patterns
+// are positive finite fp16 numbers (denormals included, which the kernels
+// preserve) ordered as the integers, so the fp16 minimum instruction
+// (v_pk_minimum3_f16) returns the u16 minimum.  The host bound keeps every
+// operand of the recurrence below 0x7c00.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_min3(uint32_t a, uint32_t b, uint32_t c)
+{
+    const f16x2 x = __builtin_bit_cast(f16x2, a), y = __builtin_bit_cast(f16x2, b),
+                z = __builtin_bit_cast(f16x2, c);
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_minimum(__builtin_elementwise_minimum(x, y), z));
+}
 __device__ __forceinline__ uint32_t pk_mad(uint32_t a, uint32_t b, uint32_t c)
 {
     return u1(v2(a) * v2(b) + v2(c));
@@ -90,6 +103,20 @@ __device__ __forceinline__ void line_start(int line, int W, int H, int dx, int d
     }
 }
 
+// Global-memory pointers (address space 1): loads through them are global
+// loads; a base that is the same in every lane sits in scalar registers.
+typedef __attribute__((address_space(1))) const char* gcptr;
+typedef __attribute__((address_space(1))) char* gptr;
+
+template <typename P>
+__device__ __forceinline__ P uniform_ptr(const void* p)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P)(((uint64_t)hi << 32) | lo);
+}
+
 // Inputs of one step (one pixel of the line) for one lane.
 struct StepIn {
     uint32_t cb;        // census of the base pixel
@@ -108,10 +135,10 @@ struct PixOff {
 // is a scalar base plus a vector offset.  Pixel t of the line sits at
 // offset0 + t * step; the steps are small signed values (24-bit products).
 struct LineAddr {
-    const char* cbase;      // census of the base view, padded row starts
-    const char* cmatch;     // census of the matching view
-    const char* prior;      // prior map (left view)
-    char* S;                // aggregated cost
+    gcptr cbase;            // census of the base view, padded row starts
+    gcptr cmatch;           // census of the matching view
+    gcptr prior;            // prior map (left view)
+    gptr S;                 // aggregated cost
     uint32_t oc0, om0, op0, os0;
     int32_t dc, dp, ds;
 
@@ -123,6 +150,8 @@ struct LineAddr {
     }
 };
 
+
+// frame and view are uniform over a workgroup, so the bases are too
 template <int D, int VIEW>
 __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x0, int y0,
                                               int d0)
@@ -130,22 +159,19 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
     LineAddr la;
     // census rows are addressed from their padded start (pixel x at x + D),
     // so every offset is non-negative
-    la.cbase = reinterpret_cast<const char*>(a.cbase[VIEW] - D +
-                                             (int64_t)frame * a.census_fstride);
-    la.cmatch = reinterpret_cast<const char*>(a.cmatch[VIEW] - D +
-                                              (int64_t)frame * a.census_fstride);
-    la.prior = VIEW == 0 ? reinterpret_cast<const char*>(a.prior +
-                                                         (int64_t)frame * a.prior_fstride)
+    la.cbase = uniform_ptr<gcptr>(a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride);
+    la.cmatch = uniform_ptr<gcptr>(a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride);
+    la.prior = VIEW == 0 ? uniform_ptr<gcptr>(a.prior + (int64_t)frame * a.prior_fstride)
                          : nullptr;
-    la.S = reinterpret_cast<char*>(a.S[VIEW] + (int64_t)frame * a.S_stride);
+    la.S = uniform_ptr<gptr>(a.S[VIEW] + (int64_t)frame * a.S_stride);
     la.oc0 = (uint32_t)(y0 * a.census_pitch + x0 + D) * 4u;
     // matching pixels: x - d (left base, descending) or x + d (right base)
     // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
     la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + 7) * 4u : la.oc0 + (uint32_t)d0 * 4u;
-    la.op0 = (uint32_t)(y0 * a.prior_pitch + x0) * 2u;
+    la.op0 = (uint32_t)(y0 * a.prior_pitch + x0) * 4u;
     la.os0 = ((uint32_t)(y0 * a.W + x0) * D + (uint32_t)d0) * 2u;
     la.dc = (a.dy * a.census_pitch + a.dx) * 4;
-    la.dp = (a.dy * a.prior_pitch + a.dx) * 2;
+    la.dp = (a.dy * a.prior_pitch + a.dx) * 4;
     la.ds = (a.dy * a.W + a.dx) * D * 2;
     return la;
 }
@@ -153,24 +179,28 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
 template <int VIEW>
 __device__ __forceinline__ void load_pixel(const LineAddr& la, const PixOff& o, StepIn& st)
 {
-    st.cb = *reinterpret_cast<const uint32_t*>(la.cbase + o.oc);
-    const char* pm = la.cmatch + o.om;
-    st.m0 = *reinterpret_cast<const u32x4a4*>(pm);
-    st.m1 = *reinterpret_cast<const u32x4a4*>(pm + 16);
+    typedef __attribute__((address_space(1))) const uint32_t* gu32;
+    typedef __attribute__((address_space(1))) const u32x4a4* gu32x4;
+    typedef __attribute__((address_space(1))) const int32_t* gi32;
+    st.cb = *reinterpret_cast<gu32>(la.cbase + o.oc);
+    const gcptr pm = la.cmatch + o.om;
+    st.m0 = *reinterpret_cast<gu32x4>(pm);
+    st.m1 = *reinterpret_cast<gu32x4>(pm + 16);
     // the left view always has a prior map
-    st.e = VIEW == 0 ? (int32_t) * reinterpret_cast<const int16_t*>(la.prior + o.op) : -1;
+    st.e = VIEW == 0 ? *reinterpret_cast<gi32>(la.prior + o.op) : -1;
 }
 
 // S streams through once per pass: non-temporal loads / stores, so it does not
 // evict the census rows that neighbouring lines re-read from L2.
 __device__ __forceinline__ u32x4 load_s(const LineAddr& la, const PixOff& o)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(la.S + o.os));
+    typedef __attribute__((address_space(1))) const u32x4* gcv;
+    return __builtin_nontemporal_load(reinterpret_cast<gcv>(la.S + o.os));
 }
 __device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, const uint32_t v[4])
 {
-    __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]},
-                                reinterpret_cast<u32x4*>(la.S + o.os));
+    typedef __attribute__((address_space(1))) u32x4* gv;
+    __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<gv>(la.S + o.os));
 }
 
 // Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
@@ -224,7 +254,7 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
 // Minimum of the lane's 8 cells, in both halves of the result.
 __device__ __forceinline__ uint32_t lane_min2(const uint32_t L[4])
 {
-    const uint32_t v = pk_min(pk_min(L[0], L[1]), pk_min(L[2], L[3]));
+    const uint32_t v = pk_min(pk_min3(L[0], L[1], L[2]), L[3]);
     return pk_min(v, __builtin_amdgcn_alignbit(v, v, 16));
 }
 
@@ -261,7 +291,7 @@ __device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t 
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
-        uint32_t best = pk_min(pk_min(L[i], nb), mp2);
+        uint32_t best = pk_min3(L[i], nb, mp2);
         L[i] = pk_add(best, pk_sub(C[i], m));
     }
     m = group_min<G>(lane_min2(L));

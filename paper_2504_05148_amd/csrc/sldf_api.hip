@@ -77,10 +77,13 @@ sldf_status validate(const sldf_params* p)
     // 16-bit bound: every L_r lies in [C', C' + P2'] (Eq. 2), the sum of the
     // paths in [|R| C', |R| (C' + P2')], and the largest intermediate of the
     // recurrence is C' + P2' + P1' (neighbour term) or m + P2' <= C' + 2 P2'.
+    // The recurrence compares its terms as fp16 bit patterns (a three-way
+    // packed minimum), exact while they stay below 0x7c00 (the fp16
+    // infinity): C' + P2' + max(P1', P2') < 0x7c00.
     int64_t cmax = max_cost(p, n);
     int64_t P1 = (int64_t)p->alpha_den * p->p1, P2 = (int64_t)p->alpha_den * p->p2;
     if ((int64_t)p->num_paths * (cmax + P2) >= 65536) return SLDF_EOVERFLOW;
-    if (cmax + P2 + (P1 > P2 ? P1 : P2) >= 65536) return SLDF_EOVERFLOW;
+    if (cmax + P2 + (P1 > P2 ? P1 : P2) >= 0x7c00) return SLDF_EOVERFLOW;
     if ((int64_t)p->alpha_num * p->q2 >= 65536) return SLDF_EOVERFLOW;
     return SLDF_OK;
 }
@@ -113,7 +116,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     const size_t cframe = cpitch * (size_t)p->height;
     void* cl = seg(F * cframe * 4);
     void* cr = seg(F * cframe * 4);
-    void* pr = p->semidense ? seg(F * px * 2) : nullptr;
+    void* pr = seg(F * px * 4);
     void* ds = seg(F * px * 2);
     void* dr = seg(F * px * 2);
     void* dsub = seg(F * px * 4);
@@ -143,7 +146,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->census_r = base ? (uint32_t*)cr + p->max_disp : nullptr;
         b->census_pitch = (int32_t)cpitch;
         b->census_fstride = (int64_t)cframe;
-        b->prior = (int16_t*)pr;
+        b->prior = (int32_t*)pr;
         b->dstar = (int16_t*)ds;
         b->dright = (int16_t*)dr;
         b->dsub = (float*)dsub;
@@ -386,10 +389,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (mark(1) != hipSuccess) return SLDF_EDEVICE;
     ctx->launches[0] += 1;
 
-    // semidensification (Sec. IV-B, SDSGM only)
-    const int16_t* prior = lidar;
-    int32_t prior_pitch = lidar_pitch;
-    int64_t prior_fstride = lidar_frame_stride;
+    // semidensification (Sec. IV-B, SDSGM only); DSGM uses D-bar itself
     if (p.semidense) {
         SemiArgs sa;
         sa.census_l = b.census_l;
@@ -408,10 +408,10 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         sa.ts = p.ts;
         sa.rs = p.rs;
         if ((e = launch_semidense(sa, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
-        prior = b.prior;
-        prior_pitch = W;
-        prior_fstride = b.px_stride;
         ctx->launches[1] += 1;
+    } else if ((e = launch_widen_prior(lidar, lidar_pitch, lidar_frame_stride, b.prior, W, H,
+                                       b.px_stride, n_frames, s)) != hipSuccess) {
+        return SLDF_EDEVICE;
     }
     if (mark(2) != hipSuccess) return SLDF_EDEVICE;
 
@@ -424,9 +424,9 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.cmatch[1] = b.census_l;
     ga.census_pitch = b.census_pitch;
     ga.census_fstride = b.census_fstride;
-    ga.prior = prior;
-    ga.prior_pitch = prior_pitch;
-    ga.prior_fstride = prior_fstride;
+    ga.prior = b.prior;
+    ga.prior_pitch = W;
+    ga.prior_fstride = b.px_stride;
     ga.S[0] = b.S_left;
     ga.S[1] = b.S_right;
     ga.wta[0] = b.dstar;
@@ -597,14 +597,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         return SLDF_EDEVICE;
     if (cp(t.rho, b.rho, px * 2) != hipSuccess || cp(t.features, b.x0, px * 16) != hipSuccess)
         return SLDF_EDEVICE;
-    if (t.prior) {
-        if (p.semidense) {
-            if (cp(t.prior, b.prior, px * 2) != hipSuccess) return SLDF_EDEVICE;
-        } else if (hipMemcpy2DAsync(t.prior, (size_t)W * 2, lidar, (size_t)lidar_pitch * 2,
-                                    (size_t)W * 2, H, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-            return SLDF_EDEVICE;
-        }
-    }
+    if (t.prior && launch_narrow_prior(b.prior, (int16_t*)t.prior, (int64_t)px, s) != hipSuccess)
+        return SLDF_EDEVICE;
     return SLDF_OK;
 }
 

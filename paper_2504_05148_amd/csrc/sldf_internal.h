@@ -17,7 +17,8 @@ struct Buffers {
     uint32_t* census_r;
     int32_t census_pitch;     // W + 2 D
     int64_t census_fstride;   // H * census_pitch
-    int16_t* prior;       // [F][H][W]  semidense map (SDSGM only)
+    int32_t* prior;       // [F][H][W] prior of the joint cost: D-hat (SDSGM) or D-bar
+                          // (DSGM), widened to 32 bits for the path passes
     int16_t* dstar;       // [F][H][W]
     int16_t* dright;      // [F][H][W]
     float* dsub;          // [F][H][W]
@@ -55,7 +56,7 @@ struct SemiArgs {
     const int16_t* lidar;
     int32_t lidar_pitch;
     int64_t lidar_fstride;
-    int16_t* out;
+    int32_t* out;
     int64_t px_stride;
     int32_t W, H, D, n, ts, rs;
 };
@@ -65,7 +66,7 @@ struct SgmArgs {
     const uint32_t* cmatch[2];  // matching-view census per view
     int32_t census_pitch;
     int64_t census_fstride;
-    const int16_t* prior;       // left-view prior (D-hat / D-bar)
+    const int32_t* prior;       // left-view prior (D-hat / D-bar), 32-bit
     int32_t prior_pitch;
     int64_t prior_fstride;
     uint16_t* S[2];             // aggregated cost per view
@@ -213,6 +214,12 @@ enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2, kSingle = 3 };
 
 hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s);
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s);
+// D-bar int16 (caller's pitch) -> 32-bit prior map (dense rows of W)
+hipError_t launch_widen_prior(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                              int32_t* out, int32_t W, int32_t H, int64_t out_fstride,
+                              int nframes, hipStream_t s);
+// 32-bit prior map of one frame -> int16 (debug tap)
+hipError_t launch_narrow_prior(const int32_t* in, int16_t* out, int64_t n, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
 // two opposite directions (dx, dy) and (-dx, -dy) in one launch

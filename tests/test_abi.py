@@ -52,13 +52,13 @@ def test_workspace_size_plan():
     W, H, D = 1242, 375, 128
     px, cells = W * H, W * H * D
     census = 2 * (W + 2 * D) * H * 4            # padded census rows, both views
-    # prior, d*, d' (i16), dsub (f32), S left + right (u16), LiDAR row masks
+    # prior (i32), d*, d' (i16), dsub (f32), S left + right (u16), LiDAR row masks
     # (D/32 words), rho (u16), cost features (2 u32), surrogate inputs (8 bf16)
     # paired-direction checkpoints: every 8 pixels of each line, D u16 per
     # checkpoint, both views; the largest pair is the diagonal one
     segs = lambda n: (n + 7) // 8
     ck = max(H * segs(W), W * segs(H), (W + H - 1) * segs(min(W, H))) * D * 2 * 2
-    exact = (census + px * (2 + 2 + 2 + 4) + 2 * cells * 2 + ck +
+    exact = (census + px * (4 + 2 + 2 + 4) + 2 * cells * 2 + ck +
              px * (D // 32 * 4 + 2 + 8 + 16))
     assert exact <= n1 < exact + 16 * 256
     p.batch = 4
@@ -123,6 +123,16 @@ def test_overflow_bound_is_tight():
     assert sldf.workspace_size(sldf.default_params(p2=697)) > 0
     with pytest.raises(sldf.SldfError):
         sldf.workspace_size(sldf.default_params(p2=698))
+
+
+def test_fp16_compare_bound_is_tight():
+    # the recurrence compares its terms as fp16 bit patterns: C'max + 2 P2'
+    # < 0x7c00 = 31744; with one path it binds before the sum bound:
+    # 1213 + 20 P2 < 31744 <=> P2 <= 1526
+    assert sldf.workspace_size(sldf.default_params(num_paths=1, p2=1526)) > 0
+    with pytest.raises(sldf.SldfError) as ei:
+        sldf.workspace_size(sldf.default_params(num_paths=1, p2=1527))
+    assert ei.value.status == sldf.EOVERFLOW
 
 
 def test_status_strings():
