@@ -10,6 +10,9 @@ paper's studies, scored with coverage / covered error / total error
   and SDSGM with the learned check;
 - LiDAR cost terms (Tab. III): the DDC against the quadratic (LiDAR-SGM)
   and Huber terms, on the sparse and on the semidense prior;
+- robustness: image noise, contrast loss and rain-like streaks, and LiDAR
+  density / scan-line sweeps (the CARLA rain and density studies), with
+  T_s = 9 as the paper uses for rain;
 - parameter sweeps: any sldf_params field (T_s, r_s, Q1, Q2, T_c, r_c, ...)
   through --sweep name=v1,v2,...
 
@@ -122,6 +125,41 @@ def prior_terms(frames) -> dict:
     return out
 
 
+# robustness workloads (the shapes of the paper's CARLA rain and density
+# studies): degraded images and LiDAR density / scan-line sweeps
+DEGRADATIONS = ("none", "noise", "contrast", "rain")
+DENSITIES = ((0.005, 16), (0.02, 32), (0.05, 64), (0.10, 128))
+ROBUST_METHODS = {
+    "SGM (census, stereo check)": dict(alpha_num=0, semidense=0, check_mode=1),
+    "DSGM": dict(semidense=0),
+    "SDSGM": dict(semidense=1),
+    "SDSGM, Ts = 9": dict(semidense=1, ts=9),
+}
+
+
+def robustness(n: int, first: int = 9000, degradations=DEGRADATIONS) -> dict:
+    """Methods under image degradations (noise, contrast, rain streaks)."""
+    rows = {}
+    for deg in degradations:
+        spec = synth.robust_spec(degrade=deg)
+        frames = [synth.make_frame(spec, synth.CONFIG_IDS["robust"], first + i) for i in range(n)]
+        for name, kw in ROBUST_METHODS.items():
+            rows[f"{deg}: {name}"] = evaluate.evaluate_frames(run_frames(frames, **kw), frames)
+    return rows
+
+
+def density_sweep(n: int, first: int = 9500, densities=DENSITIES) -> dict:
+    """DSGM and SDSGM against the LiDAR density and scan-line count."""
+    rows = {}
+    for dens, lines in densities:
+        spec = synth.robust_spec(density=dens, lines=lines)
+        frames = [synth.make_frame(spec, synth.CONFIG_IDS["robust"], first + i) for i in range(n)]
+        for name in ("DSGM", "SDSGM"):
+            rows[f"{100 * dens:g} %, {lines} lines: {name}"] = evaluate.evaluate_frames(
+                run_frames(frames, **ROBUST_METHODS[name]), frames)
+    return rows
+
+
 def sweep(frames, name: str, values) -> dict:
     return {f"{name}={v}": evaluate.evaluate_frames(run_frames(frames, **{name: v}), frames)
             for v in values}
@@ -151,6 +189,8 @@ def main(argv=None):
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--first", type=int, default=5000, help="first frame seed index")
     ap.add_argument("--sweep", action="append", default=[], metavar="NAME=V1,V2,...")
+    ap.add_argument("--robust-frames", type=int, default=0,
+                    help="frames per cell of the robustness and density tables (0 = skip)")
     args = ap.parse_args(argv)
     frames = _frames(args.frames, first=args.first)
     print(f"{args.frames} synthetic 1242x375 D=128 frames (seeds {args.first}..)\n")
@@ -158,6 +198,9 @@ def main(argv=None):
     print(table("Consistency checks on SDSGM (Tab. V shape)", check_modes(frames)), "\n")
     print(table("Method variants (Tab. I)", variants(frames, _load_surrogate())), "\n")
     print(table("LiDAR cost terms (Tab. III shape)", prior_terms(frames)), "\n")
+    if args.robust_frames > 0:
+        print(table("Robustness to image degradations", robustness(args.robust_frames)), "\n")
+        print(table("LiDAR density and scan lines", density_sweep(args.robust_frames)), "\n")
     for s in args.sweep:
         name, vals = s.split("=")
         print(table(f"Sweep of {name}", sweep(frames, name, [int(v) for v in vals.split(",")])),

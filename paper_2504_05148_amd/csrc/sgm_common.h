@@ -254,8 +254,14 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
 // Minimum of the lane's 8 cells, in both halves of the result.
 __device__ __forceinline__ uint32_t lane_min2(const uint32_t L[4])
 {
-    const uint32_t v = pk_min(pk_min3(L[0], L[1], L[2]), L[3]);
-    return pk_min(v, __builtin_amdgcn_alignbit(v, v, 16));
+    // t = min(L0, L1, L2) per half; u adds L3 and the other half of t; the
+    // last minimum with the halves swapped covers all eight cells
+    const f16x2 t = __builtin_bit_cast(f16x2, pk_min3(L[0], L[1], L[2]));
+    const f16x2 l3 = __builtin_bit_cast(f16x2, L[3]);
+    const f16x2 u = __builtin_elementwise_minimum(__builtin_elementwise_minimum(t, l3),
+                                                  __builtin_shufflevector(t, t, 1, 0));
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_minimum(u, __builtin_shufflevector(u, u, 1, 0)));
 }
 
 // One step of Eq. 2 on the lane's 8 disparities.  L holds L_r(p - r, .) on

@@ -51,3 +51,12 @@ def test_prior_terms_rows(frames):
     assert len(rows) == 2 * len(ablation.PRIOR_TERMS)
     for e in rows.values():
         assert 0.0 < e["coverage"] <= 1.0
+
+
+def test_robustness_and_density_rows():
+    rows = ablation.robustness(1, degradations=("rain",))
+    assert len(rows) == len(ablation.ROBUST_METHODS)
+    rows = ablation.density_sweep(1, densities=((0.02, 32),))
+    assert len(rows) == 2
+    for e in rows.values():
+        assert 0.0 < e["coverage"] <= 1.0
