@@ -20,7 +20,10 @@
 namespace sldf {
 
 constexpr int kSeg = 8;   // checkpoint interval (pixels per segment)
-constexpr int kRing = 4;  // depth of the census / prior prefetch ring
+// depth of the census / prior prefetch ring: 4 positions, 2 in the last pair
+// (whose WTA needs the registers; the census rows mostly come from L2)
+template <int MODE>
+constexpr int ring_depth() { return MODE == kLast ? 2 : 4; }
 
 template <int G, int MODE, int VIEW>
 __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, u32x4* cw,
@@ -29,6 +32,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     constexpr int D = G * 8;
     constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
     constexpr bool kStoreS = MODE == kFirst || MODE == kMiddle;
+    constexpr int kRing = ring_depth<MODE>();
     int x0, y0, len;
     line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
@@ -108,9 +112,9 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
         for (int j = 0; j < kSeg; ++j) {
             uint32_t C[4];
             cost(R[j % kRing], u0 + j, C);
-            // the first kRing slots move on to the rest of this segment, the
-            // others to the start of segment s - 1
-            load(R[j % kRing], j < kRing ? u0 + j + kRing : u0 - kSeg + j - kRing);
+            // the slot moves on to position j + kRing of this segment, or past
+            // its end to the start of segment s - 1
+            load(R[j % kRing], j + kRing < kSeg ? u0 + j + kRing : u0 + j + kRing - 2 * kSeg);
             cw[j * 64] = u32x4{C[0], C[1], C[2], C[3]};
             rec8<G>(Lf, mf, C, p1x2, p2x2, gfirst, glast);
 #pragma unroll
