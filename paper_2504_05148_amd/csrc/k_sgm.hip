@@ -27,11 +27,12 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
     uint32_t L[4] = {0, 0, 0, 0};   // zero state: the first step yields L = C
+    Edge edge;
     uint32_t m = 0;
     auto step = [&](const StepIn& in, const u32x4& s_in, int t) {
         uint32_t C[4];
         cost8<D, VIEW>(a, pat, in, x0 + t * a.dx, d0, C);
-        rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast);
+        rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
         const PixOff o = la.at(t);
         if (MODE == kFirst) {
             store_s(la, o, L);

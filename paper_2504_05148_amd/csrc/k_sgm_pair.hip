@@ -41,6 +41,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
         a.ckpt + (((size_t)fv * a.nlines + line) * a.ckpt_segs * G + g) * 4;
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
+    Edge edge;
 
     // The line is cut into nseg segments of kSeg positions; `pad` virtual
     // positions before pixel 0 fill the first one.  Position u maps to pixel
@@ -71,7 +72,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                 uint32_t C[4];
                 cost(R[j % kRing], q * kSeg + j, C);
                 load(R[j % kRing], q * kSeg + j + kRing);
-                rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast);
+                rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
             }
             *ckpt(q) = u32x4{L[0], L[1], L[2], L[3]};
         }
@@ -116,7 +117,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
             // its end to the start of segment s - 1
             load(R[j % kRing], j + kRing < kSeg ? u0 + j + kRing : u0 + j + kRing - 2 * kSeg);
             cw[j * 64] = u32x4{C[0], C[1], C[2], C[3]};
-            rec8<G>(Lf, mf, C, p1x2, p2x2, gfirst, glast);
+            rec8<G>(Lf, mf, C, p1x2, p2x2, gfirst, glast, edge);
 #pragma unroll
             for (int i = 0; i < 4; ++i) Lbuf[j][i] = Lf[i];
         }
@@ -124,7 +125,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
         for (int j = kSeg - 1; j >= 0; --j) {
             const u32x4 cv = cw[j * 64];
             const uint32_t C[4] = {cv.x, cv.y, cv.z, cv.w};
-            rec8<G>(Lb, mb, C, p1x2, p2x2, gfirst, glast);
+            rec8<G>(Lb, mb, C, p1x2, p2x2, gfirst, glast, edge);
             uint32_t St[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) St[i] = pk_add(Lbuf[j][i], Lb[i]);

@@ -268,18 +268,29 @@ __device__ __forceinline__ uint32_t lane_min2(const uint32_t L[4])
 // entry and L_r(p, .) on exit; m is the group minimum of L_r(p - r, .) on
 // entry and of L_r(p, .) on exit, held in both u16 halves.  A path starts
 // from L = 0, m = 0: the first step then yields L = C.
+// Neighbour exchange registers of the recurrence at D = 128 (a group is one
+// DPP row): a row shift leaves the lane at the row end unwritten, so a
+// register that starts as 0xffffffff keeps that value there for good and can
+// serve every step of every chain.
+struct Edge {
+    uint32_t pv = 0xffffffffu, nx = 0xffffffffu;
+};
+
 template <int G>
 __device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t C[4],
-                                     uint32_t p1x2, uint32_t p2x2, bool gfirst, bool glast)
+                                     uint32_t p1x2, uint32_t p2x2, bool gfirst, bool glast,
+                                     Edge& edge)
 {
     // neighbour cells d0-1 (hi half of pv) and d0+8 (lo half of nx); at the
     // ends of the disparity range the term is left out of the minimum
     uint32_t pv, nx;
     if (G == 16) {
-        // a group is one DPP row: lanes outside the row read as 0xffff, which
-        // never wins the neighbour minimum (the other neighbour is in range)
-        pv = __builtin_amdgcn_update_dpp(0xffffffffu, L[3], kRowShr1, 0xf, 0xf, false);
-        nx = __builtin_amdgcn_update_dpp(0xffffffffu, L[0], kRowShl1, 0xf, 0xf, false);
+        // lanes at the row ends read 0xffff, which never wins the neighbour
+        // minimum (the other neighbour is in range)
+        edge.pv = __builtin_amdgcn_update_dpp(edge.pv, L[3], kRowShr1, 0xf, 0xf, false);
+        edge.nx = __builtin_amdgcn_update_dpp(edge.nx, L[0], kRowShl1, 0xf, 0xf, false);
+        pv = edge.pv;
+        nx = edge.nx;
     } else {
         pv = dpp<kWaveShr1>(L[3]);
         nx = dpp<kWaveShl1>(L[0]);
