@@ -182,14 +182,13 @@ sldf_status sldf_set_taps(sldf_ctx* ctx, const sldf_taps* taps);
 
 /* Process one frame (the whole method, Fig. 1 flow).  All pointers device:
      left, right  uint8 [H][img_pitch], 16-byte aligned, img_pitch % 16 == 0
-     lidar        int16 [H][lidar_pitch], W <= lidar_pitch <= 65536, D-bar:
+     lidar        int16 [H][lidar_pitch], lidar_pitch >= W, D-bar:
                   0..D-1 or -1 (= invalid), as written by sldf_lidar_quantize;
                   other values are outside the contract (memory-safe, result
                   unspecified)
      disp_out     float [H][out_pitch]: subpixel disparity, -1.0f if invalid
      valid_out    uint8 [H][out_pitch]: 1 = consistent (Eq. 6), 0 = invalid
-   Enqueue-only on hip_stream.  Errors: EINVAL (NULL pointer / pitch < W /
-   lidar_pitch > 65536),
+   Enqueue-only on hip_stream.  Errors: EINVAL (NULL pointer / pitch < W),
    EALIGN, EDEVICE (launch failure). */
 sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
                      int32_t img_pitch, const int16_t* lidar, int32_t lidar_pitch,

@@ -4,8 +4,9 @@
 // For every pixel the set of valid raw sparse disparities inside the
 // (2 rc + 1)^2 window K_p is a D-bit mask (D / 32 words).  The row pass ORs
 // the single-bit masks of the 2 rc + 1 pixels of each row segment, the
-// column pass ORs 2 rc + 1 row masks, so the window test costs
-// O(rc) word ORs per pixel instead of (2 rc + 1)^2 compares.  From the mask
+// column pass ORs 2 rc + 1 row masks as a sliding window (a constant number
+// of word ORs per pixel), so the window test costs O(rc) operations per
+// pixel instead of (2 rc + 1)^2 compares.  From the mask
 // and d* the column pass derives rho_p = min |d* - v| over the set (65535 if
 // empty); the LiDAR half of Eq. 6 is then exactly rho_p <= Tc.
 #include "sldf_internal.h"
@@ -51,80 +52,105 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
-// column tile: TW x (256 / TW) pixels; narrower for wider masks so that the
-// LDS tile stays <= 40 KB at rc = 31
-template <int NW> struct ColTile { static constexpr int TW = NW >= 8 ? 16 : 32; };
+// Column pass: the window mask of pixel (x, y) is the OR of the row masks of
+// rows y - rc .. y + rc.  Sliding-window OR by the van Herk / Gil-Werman
+// scheme: with L = 2 rc + 1, a block takes a band of L output rows; the
+// window of output row t (band rows t .. t + L - 1 of the input rows
+// y0 - rc ..) is the OR of the suffix of the first L input rows from t and
+// the prefix of the next L rows up to t + L - 1.  Each input row is read
+// twice per band (suffix scan and prefix scan) instead of L times.
+// Thread = (column, mask word): lane c NW + w holds word w of column c; the
+// nearest-set-bit search runs per word and is reduced over the NW lanes.
+constexpr int kColT = 128;   // threads per column-pass block (small: many blocks per CU)
 
 template <int NW>
-__global__ __launch_bounds__(256) void lidar_colbits_kernel(LidarArgs a)
+__global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
 {
-    constexpr int TW = ColTile<NW>::TW, TH = 256 / TW;
-    extern __shared__ uint32_t tile[];   // [(TH + 2 rc)][TW][NW]
-    const int frame = blockIdx.z, rc = a.rc;
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
-    const int rows = TH + 2 * rc;
-    const uint32_t* rb = a.rowbits + (int64_t)frame * a.H * a.W * NW;
-    for (int i = threadIdx.x; i < rows * TW * (NW / 2); i += 256) {
-        const int q = i % (NW / 2), c = (i / (NW / 2)) % TW, r = i / ((NW / 2) * TW);
-        const int gy = y0 - rc + r, gx = x0 + c;
-        uint2 v = make_uint2(0, 0);
-        if (gy >= 0 && gy < a.H && gx < a.W)
-            v = *reinterpret_cast<const uint2*>(rb + ((int64_t)gy * a.W + gx) * NW + 2 * q);
-        *reinterpret_cast<uint2*>(tile + (r * TW + c) * NW + 2 * q) = v;
-    }
-    __syncthreads();
-    const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= a.W || y >= a.H) return;
-    uint32_t B[NW];
+    extern __shared__ uint32_t hbuf[];   // [L][kColT] suffix ORs of the first L rows
+    constexpr int TC = kColT / NW;
+    const int rc = a.rc, L = 2 * rc + 1;
+    const int w = threadIdx.x % NW, c = threadIdx.x / NW;
+    const int x = blockIdx.x * TC + c, y0 = blockIdx.y * L, frame = blockIdx.z;
+    const bool xin = x < a.W;
+    const uint32_t* rb = a.rowbits + (int64_t)frame * a.H * a.W * NW + w;
+    auto row = [&](int r) -> uint32_t {
+        const int gy = y0 - rc + r;
+        return (xin && gy >= 0 && gy < a.H) ? rb[((int64_t)gy * a.W + x) * NW] : 0u;
+    };
+    // loads in chunks of kC rows, so that a chunk's loads are in flight
+    // together instead of one dependent load per row
+    constexpr int kC = 16;
+    uint32_t h = 0u;
+    for (int base = L - 1; base >= 0; base -= kC) {
+        uint32_t v[kC];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) B[j] = 0u;
-    for (int r = 0; r <= 2 * rc; ++r) {
-        const uint32_t* t = tile + ((ty + r) * TW + tx) * NW;
+        for (int k = 0; k < kC; ++k) v[k] = base - k >= 0 ? row(base - k) : 0u;
 #pragma unroll
-        for (int j = 0; j < NW; j += 2) {
-            uint2 v = *reinterpret_cast<const uint2*>(t + j);
-            B[j] |= v.x;
-            B[j + 1] |= v.y;
+        for (int k = 0; k < kC; ++k) {
+            if (base - k < 0) break;
+            h |= v[k];
+            hbuf[(base - k) * kColT + threadIdx.x] = h;
         }
     }
-    const int64_t px = (int64_t)frame * a.px_stride + (int64_t)y * a.W + x;
-    const int d = a.dstar[px];
-    const int w0 = d >> 5, b0 = d & 31;
-    int up = 0xffff, dn = 0xffff;
-    // nearest set bit at index >= d
+    uint32_t g = 0u;
+    const int lo = 32 * w;
+    const bool owner = xin && w == 0;
+    const int64_t px0 = (int64_t)frame * a.px_stride + (int64_t)y0 * a.W + x;
+    constexpr int kF = 8;
+    for (int t0 = 0; t0 < L; t0 += kF) {
+        uint32_t v[kF], s01[kF], cv[kF];
+        int dv[kF];
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-        uint32_t m = j < w0 ? 0u : (j == w0 ? (B[j] & (0xffffffffu << b0)) : B[j]);
-        if (up == 0xffff && m) up = 32 * j + __builtin_ctz(m) - d;
-    }
-    // nearest set bit at index <= d
+        for (int k = 0; k < kF; ++k) {
+            const int t = t0 + k;
+            const bool in = t < L && y0 + t < a.H && xin;
+            const int64_t px = px0 + (int64_t)t * a.W;
+            v[k] = t > 0 && t < L ? row(t + L - 1) : 0u;
+            dv[k] = in ? a.dstar[px] : 0;
+            s01[k] = in && w == 0 && a.x0 ? a.feat[2 * px] : 0u;
+            cv[k] = in && w == 0 && a.x0 ? a.feat[2 * px + 1] : 0u;
+        }
 #pragma unroll
-    for (int j = NW - 1; j >= 0; --j) {
-        uint32_t m = j > w0 ? 0u : (j == w0 ? (B[j] & (0xffffffffu >> (31 - b0))) : B[j]);
-        if (dn == 0xffff && m) dn = d - (32 * j + 31 - __builtin_clz(m));
-    }
-    const int rho = up < dn ? up : dn;
-    a.rho[px] = (uint16_t)rho;
-    if (a.x0) {
-        // surrogate inputs: S(d*), second minimum, curvature, d*, residual,
-        // each an integer times a float32 scale, stored as bf16 (RNE)
-        const uint32_t s01 = a.feat[2 * px];
-        const int curv = (int)a.feat[2 * px + 1];
-        const int r = rho < 32 ? rho : 32;
-        uint16_t f[8];
-        f[0] = f32_to_bf16_rne((float)(s01 & 0xffffu) * a.sS);
-        f[1] = f32_to_bf16_rne((float)(s01 >> 16) * a.sS);
-        f[2] = f32_to_bf16_rne((float)curv * a.sS);
-        f[3] = f32_to_bf16_rne((float)d * a.sD);
-        f[4] = f32_to_bf16_rne((float)r * a.sR);
-        f[5] = f[6] = f[7] = 0;
-        uint4 v;
-        v.x = f[0] | ((uint32_t)f[1] << 16);
-        v.y = f[2] | ((uint32_t)f[3] << 16);
-        v.z = f[4];
-        v.w = 0;
-        *reinterpret_cast<uint4*>(a.x0 + 8 * px) = v;
+        for (int k = 0; k < kF; ++k) {
+            const int t = t0 + k;
+            if (t >= L || y0 + t >= a.H) break;
+            g |= v[k];
+            const uint32_t m = hbuf[t * kColT + threadIdx.x] | g;
+            const int d = dv[k];
+            // this word's nearest set bits at index >= d and <= d
+            const uint32_t mu = d < lo ? m : (d - lo < 32 ? m & (0xffffffffu << (d - lo)) : 0u);
+            const uint32_t md =
+                d < lo ? 0u : (d - lo < 32 ? m & (0xffffffffu >> (31 - (d - lo))) : m);
+            const int up = mu ? lo + __builtin_ctz(mu) - d : 0xffff;
+            const int dn = md ? d - (lo + 31 - __builtin_clz(md)) : 0xffff;
+            int rho = up < dn ? up : dn;
+#pragma unroll
+            for (int q = 1; q < NW; q <<= 1) {
+                const int o = __shfl_xor(rho, q, NW);
+                rho = o < rho ? o : rho;
+            }
+            if (!owner) continue;
+            const int64_t px = px0 + (int64_t)t * a.W;
+            a.rho[px] = (uint16_t)rho;
+            if (a.x0) {
+                // surrogate inputs: S(d*), second minimum, curvature, d*,
+                // residual, each an integer times a float32 scale, stored as
+                // bf16 (RNE)
+                const int r = rho < 32 ? rho : 32;
+                uint16_t f[5];
+                f[0] = f32_to_bf16_rne((float)(s01[k] & 0xffffu) * a.sS);
+                f[1] = f32_to_bf16_rne((float)(s01[k] >> 16) * a.sS);
+                f[2] = f32_to_bf16_rne((float)(int)cv[k] * a.sS);
+                f[3] = f32_to_bf16_rne((float)d * a.sD);
+                f[4] = f32_to_bf16_rne((float)r * a.sR);
+                uint4 o;
+                o.x = f[0] | ((uint32_t)f[1] << 16);
+                o.y = f[2] | ((uint32_t)f[3] << 16);
+                o.z = f[4];
+                o.w = 0;
+                *reinterpret_cast<uint4*>(a.x0 + 8 * px) = o;
+            }
+        }
     }
 }
 
@@ -137,15 +163,16 @@ hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s)
     else hipLaunchKernelGGL(lidar_rowbits_kernel<8>, g1, dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    auto col = [&](auto kern, int TW) {
-        const int TH = 256 / TW;
-        dim3 g2((a.W + TW - 1) / TW, (a.H + TH - 1) / TH, nframes);
-        const size_t lds = (size_t)(TH + 2 * a.rc) * TW * NW * 4;
-        hipLaunchKernelGGL(kern, g2, dim3(256), lds, s, a);
+    // a band of L = 2 rc + 1 rows per block, kColT / NW columns
+    const int L = 2 * a.rc + 1;
+    auto col = [&](auto kern) {
+        const int TC = kColT / NW;
+        dim3 g2((a.W + TC - 1) / TC, (a.H + L - 1) / L, nframes);
+        hipLaunchKernelGGL(kern, g2, dim3(kColT), (size_t)L * kColT * 4, s, a);
     };
-    if (NW == 2) col(lidar_colbits_kernel<2>, ColTile<2>::TW);
-    else if (NW == 4) col(lidar_colbits_kernel<4>, ColTile<4>::TW);
-    else col(lidar_colbits_kernel<8>, ColTile<8>::TW);
+    if (NW == 2) col(lidar_colbits_kernel<2>);
+    else if (NW == 4) col(lidar_colbits_kernel<4>);
+    else col(lidar_colbits_kernel<8>);
     return hipGetLastError();
 }
 

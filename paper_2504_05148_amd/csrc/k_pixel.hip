@@ -120,6 +120,16 @@ hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s)
 // ---------------------------------------------------------------------------
 constexpr int kSemiT = 16, kSemiMaxR = 15, kSemiLT = kSemiT + 2 * kSemiMaxR, kSemiMaxD = 256;
 
+// Prior e of pixel (x, y) of frame f: its word for the path passes and, for
+// frame 0, the debug tap.
+__device__ __forceinline__ void emit_prior(const PriorOut& o, int f, int x, int y, int16_t e,
+                                           int D)
+{
+    o.words[f * o.fstride + (int64_t)(y + 1) * o.pitch + x + 1] =
+        prior_word(e, D, o.w_prior, o.w_noprior);
+    if (o.tap && f == 0) o.tap[(int64_t)y * (o.pitch - 2) + x] = e;
+}
+
 __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
 {
     __shared__ int16_t tile[kSemiLT][kSemiLT];
@@ -131,23 +141,49 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     const int rs = a.rs, lt = kSemiT + 2 * rs, D = a.D;
     const int x0 = blockIdx.x * kSemiT, y0 = blockIdx.y * kSemiT;
     if (threadIdx.x == 0) ncand = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < lt * lt; i += 256) {
-        int r = i / lt, c = i - r * lt;
-        int gy = y0 - rs + r, gx = x0 - rs + c;
-        int16_t v = -1;
-        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = lid[(int64_t)gy * a.lidar_pitch + gx];
-        tile[r][c] = v;
-        // values outside [0, D) are no candidates (the ABI admits only -1)
-        if ((unsigned)v < (unsigned)D) cand[atomicAdd(&ncand, 1)] = (r << 16) | (c << 8) | v;
+    // all staging loads of a thread are issued before its LDS writes, so
+    // that they are in flight together
+    constexpr int kTileK = (kSemiLT * kSemiLT + 255) / 256;
+    constexpr int kRowK = (kSemiT * (kSemiMaxD + kSemiT) + 255) / 256;
+    int16_t tv[kTileK];
+#pragma unroll
+    for (int k = 0; k < kTileK; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int r = i / lt, c = i - r * lt;
+        const int gy = y0 - rs + r, gx = x0 - rs + c;
+        tv[k] = (i < lt * lt && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                    ? lid[(int64_t)gy * a.lidar_pitch + gx]
+                    : (int16_t)-1;
     }
     // census rows are padded by D codes on each side: columns down to -D are
     // inside the buffer
     const uint32_t* crb = a.census_r + (int64_t)frame * a.census_fstride;
     const int cw = D + kSemiT - 1;
-    for (int i = threadIdx.x; i < kSemiT * cw; i += 256) {
-        const int r = i / cw, k = i - r * cw, gy = y0 + r;
-        crow[r][k] = gy < a.H ? crb[(int64_t)gy * a.census_pitch + x0 - D + 1 + k] : 0u;
+    uint32_t cv[kRowK];
+#pragma unroll
+    for (int k = 0; k < kRowK; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int r = i / cw, q = i - r * cw, gy = y0 + r;
+        cv[k] = (i < kSemiT * cw && gy < a.H)
+                    ? crb[(int64_t)gy * a.census_pitch + x0 - D + 1 + q]
+                    : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kTileK; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= lt * lt) break;
+        const int r = i / lt, c = i - r * lt;
+        const int16_t v = tv[k];
+        tile[r][c] = v;
+        // values outside [0, D) are no candidates (the ABI admits only -1)
+        if ((unsigned)v < (unsigned)D) cand[atomicAdd(&ncand, 1)] = (r << 16) | (c << 8) | v;
+    }
+#pragma unroll
+    for (int k = 0; k < kRowK; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= kSemiT * cw) break;
+        crow[i / cw][i % cw] = cv[k];
     }
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -180,39 +216,67 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     }
     int16_t outv = lid[(int64_t)y * a.lidar_pitch + x];
     if ((best >> 16) < (uint32_t)a.ts) outv = (int16_t)(best & 0xffffu);
-    a.out[(int64_t)frame * a.px_stride + (int64_t)y * a.W + x] = outv;
+    emit_prior(a.out, frame, x, y, outv, D);
 }
 
-// The path passes read the prior as one 32-bit word per pixel: DSGM widens
-// the caller's D-bar map, the debug tap narrows it back.
-__global__ void widen_prior_kernel(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
-                                   int32_t* out, int32_t W, int32_t H, int64_t out_fstride)
+// DSGM: the prior is D-bar itself.
+__global__ void prior_words_kernel(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                                   PriorOut out, int32_t W, int32_t D)
 {
     const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, f = blockIdx.z;
     if (x >= W) return;
-    out[(int64_t)f * out_fstride + (int64_t)y * W + x] =
-        in[(int64_t)f * in_fstride + (int64_t)y * in_pitch + x];
+    emit_prior(out, f, x, y, in[(int64_t)f * in_fstride + (int64_t)y * in_pitch + x], D);
 }
 
-hipError_t launch_widen_prior(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
-                              int32_t* out, int32_t W, int32_t H, int64_t out_fstride,
+hipError_t launch_prior_words(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                              const PriorOut& out, int32_t W, int32_t H, int32_t D,
                               int nframes, hipStream_t s)
 {
-    hipLaunchKernelGGL(widen_prior_kernel, dim3((W + 255) / 256, H, nframes), dim3(256), 0, s,
-                       in, in_pitch, in_fstride, out, W, H, out_fstride);
+    hipLaunchKernelGGL(prior_words_kernel, dim3((W + 255) / 256, H, nframes), dim3(256), 0, s,
+                       in, in_pitch, in_fstride, out, W, D);
     return hipGetLastError();
 }
 
-__global__ void narrow_prior_kernel(const int32_t* in, int16_t* out, int64_t n)
+// Guard rings (cost weight 0) of the left-view maps, blockIdx.y = frame:
+// the top and bottom rows, then the two side columns.
+__global__ void prior_rings_kernel(PriorOut out, int32_t W, int32_t H, int32_t D)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) out[i] = (int16_t)in[i];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int P = W + 2, f = blockIdx.y;
+    if (i >= 2 * P + 2 * H) return;
+    int gx, gy;
+    if (i < 2 * P) {
+        gx = i % P;
+        gy = i < P ? 0 : H + 1;
+    } else {
+        const int k = i - 2 * P;
+        gx = k < H ? 0 : W + 1;
+        gy = 1 + (k < H ? k : k - H);
+    }
+    out.words[f * out.fstride + (int64_t)gy * P + gx] = guard_word(D);
 }
 
-hipError_t launch_narrow_prior(const int32_t* in, int16_t* out, int64_t n, hipStream_t s)
+// The right view's shared map: no prior anywhere, weight w inside, 0 on the
+// ring.
+__global__ void prior_right_kernel(uint32_t* right, uint32_t w, int32_t W, int32_t H, int32_t D)
 {
-    hipLaunchKernelGGL(narrow_prior_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       in, out, n);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int P = W + 2;
+    if (i >= P * (H + 2)) return;
+    const int gx = i % P, gy = i / P;
+    const bool ring = gx == 0 || gx == W + 1 || gy == 0 || gy == H + 1;
+    right[i] = ring ? guard_word(D) : prior_word(-1, D, w, w);
+}
+
+hipError_t launch_prior_guards(const PriorOut& out, uint32_t* right, uint32_t w_right,
+                               int32_t W, int32_t H, int32_t D, int nframes, hipStream_t s)
+{
+    const int ring = 2 * (W + 2) + 2 * H, n = (W + 2) * (H + 2);
+    hipLaunchKernelGGL(prior_rings_kernel, dim3((ring + 255) / 256, nframes), dim3(256), 0, s,
+                       out, W, H, D);
+    if (right)
+        hipLaunchKernelGGL(prior_right_kernel, dim3((n + 255) / 256), dim3(256), 0, s, right,
+                           w_right, W, H, D);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     uint32_t m = 0;
     auto step = [&](const StepIn& in, const u32x4& s_in, int t) {
         uint32_t C[4];
-        cost8<D, VIEW>(a, pat, in, x0 + t * a.dx, d0, C);
+        cost8<D, VIEW>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x0 + t * a.dx, d0, C);
         rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
         const PixOff o = la.at(t);
         if (MODE == kFirst) {
@@ -82,7 +82,7 @@ template <int G, int MODE>
 __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
 {
     constexpr int D = G * 8;
-    __shared__ uint32_t pat[2 * (D + 8) + 4];
+    __shared__ uint32_t pat[pattern_words(D)];
     build_pattern<D>(a, pat);
     __syncthreads();
     // XCD-aware mapping: blocks are dispatched round-robin over the 8 XCDs

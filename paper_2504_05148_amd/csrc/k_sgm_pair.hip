@@ -45,15 +45,17 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
 
     // The line is cut into nseg segments of kSeg positions; `pad` virtual
     // positions before pixel 0 fill the first one.  Position u maps to pixel
-    // t = u - pad.  Virtual positions have cost 0 (see cost8) and load pixel
-    // 0, so every step below runs unconditionally; only S stores and the
-    // WTA are skipped for them.
+    // t = u - pad.  Virtual positions (and prefetches before the line) read
+    // the position t = -1 before the line start, whose cost is 0 (see
+    // cost8), so every step below runs unconditionally; only S stores and
+    // the WTA are skipped for them.
     const int nseg = (len + kSeg - 1) / kSeg;
     const int pad = nseg * kSeg - len;
-    auto pix = [&](int u) { return la.at(max(u - pad, 0)); };
-    auto load = [&](StepIn& b, int u) { load_pixel<VIEW>(la, pix(u), b); };
+    const char* patl = reinterpret_cast<const char*>(pat) + 2 * d0;
+    auto load = [&](StepIn& b, int u) { load_pixel<VIEW>(la, la.at(max(u - pad, -1)), b); };
+    auto sat = [&](int u) { return la.at(max(u - pad, 0)); };
     auto cost = [&](const StepIn& in, int u, uint32_t C[4]) {
-        cost8<D, VIEW>(a, pat, in, x0 + (u - pad) * a.dx, d0, C, u >= pad);
+        cost8<D, VIEW>(a, patl, in, x0 + (u - pad) * a.dx, d0, C);
     };
     auto ckpt = [&](int q) { return reinterpret_cast<u32x4*>(ck + (size_t)q * G * 4); };
 
@@ -86,7 +88,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     u32x4 Sin[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j)
-        Sin[j] = kLoadS ? load_s(la, pix((nseg - 1) * kSeg + j)) : u32x4{0u, 0u, 0u, 0u};
+        Sin[j] = kLoadS ? load_s(la, sat((nseg - 1) * kSeg + j)) : u32x4{0u, 0u, 0u, 0u};
     // forward state entering a segment: its checkpoint (zero for the first
     // segment), with the group minimum; prepared one iteration ahead
     uint32_t Ln[4], mn;
@@ -145,7 +147,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                     wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px);
                 }
             }
-            if (kLoadS) Sin[j] = load_s(la, pix(u - kSeg));
+            if (kLoadS) Sin[j] = load_s(la, sat(u - kSeg));
         }
         enter(cin, s == 1);
     }
@@ -155,7 +157,7 @@ template <int G, int MODE>
 __global__ __launch_bounds__(256) void sgm_pair_kernel(SgmArgs a)
 {
     constexpr int D = G * 8;
-    __shared__ uint32_t pat[2 * (D + 8) + 4];
+    __shared__ uint32_t pat[pattern_words(D)];
     __shared__ u32x4 cbuf[256 / 64][kSeg][64];   // per wave: segment costs
     build_pattern<D>(a, pat);
     __syncthreads();

@@ -121,7 +121,7 @@ __device__ __forceinline__ P uniform_ptr(const void* p)
 struct StepIn {
     uint32_t cb;        // census of the base pixel
     u32x4a4 m0, m1;     // census of 8 consecutive matching pixels
-    int32_t e;          // prior disparity (-1 = none)
+    uint32_t w;         // prior word of the pixel (sldf_internal.h)
 };
 
 // Byte offsets of one pixel for one lane: census of the base pixel, census
@@ -134,10 +134,13 @@ struct PixOff {
 // workgroup (one frame-view), the offsets 32-bit byte offsets, so every load
 // is a scalar base plus a vector offset.  Pixel t of the line sits at
 // offset0 + t * step; the steps are small signed values (24-bit products).
+// Census and prior words may be read at t = -1, the position before the
+// line start: it lies in the census row pads / guard rows and on the guard
+// ring of the prior words (cost weight 0); S only at t >= 0.
 struct LineAddr {
-    gcptr cbase;            // census of the base view, padded row starts
+    gcptr cbase;            // census of the base view, guard row, padded row starts
     gcptr cmatch;           // census of the matching view
-    gcptr prior;            // prior map (left view)
+    gcptr prior;            // prior words, guard corner
     gptr S;                 // aggregated cost
     uint32_t oc0, om0, op0, os0;
     int32_t dc, dp, ds;
@@ -157,21 +160,22 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
                                               int d0)
 {
     LineAddr la;
-    // census rows are addressed from their padded start (pixel x at x + D),
-    // so every offset is non-negative
-    la.cbase = uniform_ptr<gcptr>(a.cbase[VIEW] - D + (int64_t)frame * a.census_fstride);
-    la.cmatch = uniform_ptr<gcptr>(a.cmatch[VIEW] - D + (int64_t)frame * a.census_fstride);
-    la.prior = VIEW == 0 ? uniform_ptr<gcptr>(a.prior + (int64_t)frame * a.prior_fstride)
-                         : nullptr;
+    // census rows are addressed from the padded start of the row before
+    // (pixel (x, y) at row y + 1, column x + D), so every offset down to
+    // t = -1 is non-negative
+    const int64_t crow = D + (int64_t)a.census_pitch;
+    la.cbase = uniform_ptr<gcptr>(a.cbase[VIEW] - crow + (int64_t)frame * a.census_fstride);
+    la.cmatch = uniform_ptr<gcptr>(a.cmatch[VIEW] - crow + (int64_t)frame * a.census_fstride);
+    la.prior = uniform_ptr<gcptr>(a.pword[VIEW] + (int64_t)frame * a.pword_fstride[VIEW]);
     la.S = uniform_ptr<gptr>(a.S[VIEW] + (int64_t)frame * a.S_stride);
-    la.oc0 = (uint32_t)(y0 * a.census_pitch + x0 + D) * 4u;
+    la.oc0 = (uint32_t)((y0 + 1) * a.census_pitch + x0 + D) * 4u;
     // matching pixels: x - d (left base, descending) or x + d (right base)
     // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
     la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + 7) * 4u : la.oc0 + (uint32_t)d0 * 4u;
-    la.op0 = (uint32_t)(y0 * a.prior_pitch + x0) * 4u;
+    la.op0 = (uint32_t)((y0 + 1) * a.pword_pitch + x0 + 1) * 4u;
     la.os0 = ((uint32_t)(y0 * a.W + x0) * D + (uint32_t)d0) * 2u;
     la.dc = (a.dy * a.census_pitch + a.dx) * 4;
-    la.dp = (a.dy * a.prior_pitch + a.dx) * 4;
+    la.dp = (a.dy * a.pword_pitch + a.dx) * 4;
     la.ds = (a.dy * a.W + a.dx) * D * 2;
     return la;
 }
@@ -181,13 +185,11 @@ __device__ __forceinline__ void load_pixel(const LineAddr& la, const PixOff& o, 
 {
     typedef __attribute__((address_space(1))) const uint32_t* gu32;
     typedef __attribute__((address_space(1))) const u32x4a4* gu32x4;
-    typedef __attribute__((address_space(1))) const int32_t* gi32;
     st.cb = *reinterpret_cast<gu32>(la.cbase + o.oc);
     const gcptr pm = la.cmatch + o.om;
     st.m0 = *reinterpret_cast<gu32x4>(pm);
     st.m1 = *reinterpret_cast<gu32x4>(pm + 16);
-    // the left view always has a prior map
-    st.e = VIEW == 0 ? *reinterpret_cast<gi32>(la.prior + o.op) : -1;
+    st.w = *reinterpret_cast<gu32>(la.prior + o.op);
 }
 
 // S streams through once per pass: non-temporal loads / stores, so it does not
@@ -204,15 +206,18 @@ __device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, con
 }
 
 // Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
-// denominator): (den - num) H + num DDC, H = popcount of the census xor, n
-// where the matching pixel leaves the image; DDC from the LDS pattern table
-// (entry d - e + D), a zero run for pixels without prior.  A pixel that is
-// not `real` (padding before the start of a line) gets cost 0: from a zero
-// state L = 0, m = 0 such a step leaves the state at zero, so the first real
-// pixel then yields L = C as Eq. 2 starts a path.
+// denominator): w H + num DDC with H = popcount of the census xor (n where
+// the matching pixel leaves the image), the weight w and the DDC table entry
+// from the pixel's prior word (sldf_internal.h).  The prior term is read from
+// the LDS table at patl (the lane's first entry, pattern + 2 d0 bytes) plus
+// the word's offset; the right view has no prior term.  On the guard ring the
+// weight is 0 and the entry a zero run, so the virtual positions before a
+// line start cost 0: from a zero state L = 0, m = 0 such a step leaves the
+// state at zero, and the first real pixel then yields L = C as Eq. 2 starts
+// a path.
 template <int D, int VIEW>
-__device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, const StepIn& in,
-                                      int x, int d0, uint32_t C[4], bool real = true)
+__device__ __forceinline__ void cost8(const SgmArgs& a, const char* patl, const StepIn& in,
+                                      int x, int d0, uint32_t C[4])
 {
     uint32_t mc[8];
     if (VIEW == 0) {
@@ -226,28 +231,23 @@ __device__ __forceinline__ void cost8(const SgmArgs& a, const uint32_t* pat, con
 #pragma unroll
     for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
     if (VIEW == 0 ? x < d0 + 7 : x + d0 + 7 >= a.W) {
+        // distance of the lane's first matching pixel from the image edge;
+        // opaque, so that the compiler derives the eight tests here instead
+        // of carrying eight induction variables through every step
+        int k = VIEW == 0 ? x - d0 : a.W - 1 - x - d0;
+        asm volatile("" : "+v"(k));
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const bool out = VIEW == 0 ? x - d0 - j < 0 : x + d0 + j >= a.W;
-            h[j] = out ? (uint32_t)a.n : h[j];
-        }
+        for (int j = 0; j < 8; ++j) h[j] = k < j ? (uint32_t)a.n : h[j];
     }
+    // the weight (low half of the word) multiplies both halves
+    const u16x2 wt = __builtin_shufflevector(v2(in.w), v2(in.w), 0, 0);
     if (VIEW == 0) {
-        // values outside [0, D) carry no prior (the ABI only admits -1)
-        const bool has = real && (unsigned)in.e < (unsigned)D;
-        const uint32_t mulh =
-            real ? (has ? a.mulh_prior : a.mulh_noprior) * 0x10001u : 0u;
-        // entry d0 - e + D (>= 1 with a prior): odd entries start in the
-        // second half of the table
-        const int sidx = (d0 + D) - in.e;
-        const int base = has ? (sidx >> 1) + ((sidx & 1) ? D + 8 : 0) : 2 * (D + 8);
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(patl + (in.w >> 16));
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, pat[base + i]);
+        for (int i = 0; i < 4; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt + v2(p[i]));
     } else {
-        const uint32_t mulh = real ? a.mulh_noprior * 0x10001u : 0u;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) C[i] = pk_mad(h[2 * i] | (h[2 * i + 1] << 16), mulh, 0u);
+        for (int i = 0; i < 4; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt);
     }
 }
 
@@ -385,12 +385,12 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
 // the DDC of Eq. 4 (0 at the prior, Q1 at +-1, Q2 beyond) or, by
 // prior_cost, the quadratic min(Q1 t^2, Q2) or Huber min(Q1 h_k(t), Q2)
 // terms; stored as pairs of u16 starting at even (first half) and odd
-// (second half) entries, followed by a run of zeros used where a pixel has
-// no prior.
+// (second half) entries, followed by a run of D / 2 zero words used where a
+// pixel has no prior (the layout prior_word addresses).
 template <int D>
 __device__ __forceinline__ void build_pattern(const SgmArgs& a, uint32_t* pat)
 {
-    for (int i = threadIdx.x; i < 2 * (D + 8) + 4; i += blockDim.x) {
+    for (int i = threadIdx.x; i < pattern_words(D); i += blockDim.x) {
         uint32_t v[2] = {0u, 0u};
         if (i < 2 * (D + 8)) {
             const int half = i >= D + 8;

@@ -114,9 +114,13 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     };
     const size_t cpitch = (size_t)p->width + 2 * (size_t)p->max_disp;
     const size_t cframe = cpitch * (size_t)p->height;
-    void* cl = seg(F * cframe * 4);
-    void* cr = seg(F * cframe * 4);
-    void* pr = seg(F * px * 4);
+    // census: one guard row before frame 0 and after the last frame
+    void* cl = seg((F * cframe + 2 * cpitch) * 4);
+    void* cr = seg((F * cframe + 2 * cpitch) * 4);
+    // prior words with a one-pixel guard ring; the right view's map is shared
+    const size_t pwf = ((size_t)p->width + 2) * ((size_t)p->height + 2);
+    void* pr = seg(F * pwf * 4);
+    void* prr = needs_right(p) ? seg(pwf * 4) : nullptr;
     void* ds = seg(F * px * 2);
     void* dr = seg(F * px * 2);
     void* dsub = seg(F * px * 4);
@@ -142,11 +146,14 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* logits = learned ? seg(F * px * 4) : nullptr;
     void* counter = learned ? seg(F * 4) : nullptr;
     if (b) {
-        b->census_l = base ? (uint32_t*)cl + p->max_disp : nullptr;
-        b->census_r = base ? (uint32_t*)cr + p->max_disp : nullptr;
+        b->census_l = base ? (uint32_t*)cl + cpitch + p->max_disp : nullptr;
+        b->census_r = base ? (uint32_t*)cr + cpitch + p->max_disp : nullptr;
         b->census_pitch = (int32_t)cpitch;
         b->census_fstride = (int64_t)cframe;
-        b->prior = (int32_t*)pr;
+        b->pword[0] = (uint32_t*)pr;
+        b->pword[1] = (uint32_t*)prr;
+        b->pword_pitch = p->width + 2;
+        b->pword_fstride = (int64_t)pwf;
         b->dstar = (int16_t*)ds;
         b->dright = (int16_t*)dr;
         b->dsub = (float*)dsub;
@@ -339,8 +346,6 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (!left || !right || !lidar || !disp_out || !valid_out) return SLDF_EINVAL;
     if (img_pitch < p.width || lidar_pitch < p.width || out_pitch < p.width)
         return SLDF_EINVAL;
-    // the path passes address the prior map with 32-bit byte offsets
-    if (lidar_pitch > 65536) return SLDF_EINVAL;
     if (n_frames > 1) {
         if (img_frame_stride < (int64_t)img_pitch * p.height ||
             lidar_frame_stride < (int64_t)lidar_pitch * p.height ||
@@ -389,7 +394,17 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (mark(1) != hipSuccess) return SLDF_EDEVICE;
     ctx->launches[0] += 1;
 
-    // semidensification (Sec. IV-B, SDSGM only); DSGM uses D-bar itself
+    // prior words: semidensification (Sec. IV-B, SDSGM only) or D-bar
+    // itself (DSGM), guard rings, the right view's shared map
+    PriorOut po;
+    po.words = b.pword[0];
+    po.pitch = b.pword_pitch;
+    po.fstride = b.pword_fstride;
+    po.w_prior = (uint32_t)(p.alpha_den - p.alpha_num);
+    po.w_noprior = (uint32_t)(p.blend_mode ? p.alpha_den : p.alpha_den - p.alpha_num);
+    po.tap = (int16_t*)ctx->taps.prior;
+    if (launch_prior_guards(po, b.pword[1], po.w_noprior, W, H, D, n_frames, s) != hipSuccess)
+        return SLDF_EDEVICE;
     if (p.semidense) {
         SemiArgs sa;
         sa.census_l = b.census_l;
@@ -399,8 +414,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         sa.lidar = lidar;
         sa.lidar_pitch = lidar_pitch;
         sa.lidar_fstride = lidar_frame_stride;
-        sa.out = b.prior;
-        sa.px_stride = b.px_stride;
+        sa.out = po;
         sa.W = W;
         sa.H = H;
         sa.D = D;
@@ -409,8 +423,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         sa.rs = p.rs;
         if ((e = launch_semidense(sa, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
         ctx->launches[1] += 1;
-    } else if ((e = launch_widen_prior(lidar, lidar_pitch, lidar_frame_stride, b.prior, W, H,
-                                       b.px_stride, n_frames, s)) != hipSuccess) {
+    } else if ((e = launch_prior_words(lidar, lidar_pitch, lidar_frame_stride, po, W, H, D,
+                                       n_frames, s)) != hipSuccess) {
         return SLDF_EDEVICE;
     }
     if (mark(2) != hipSuccess) return SLDF_EDEVICE;
@@ -424,9 +438,11 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.cmatch[1] = b.census_l;
     ga.census_pitch = b.census_pitch;
     ga.census_fstride = b.census_fstride;
-    ga.prior = b.prior;
-    ga.prior_pitch = W;
-    ga.prior_fstride = b.px_stride;
+    ga.pword[0] = b.pword[0];
+    ga.pword[1] = b.pword[1];
+    ga.pword_pitch = b.pword_pitch;
+    ga.pword_fstride[0] = b.pword_fstride;
+    ga.pword_fstride[1] = 0;
     ga.S[0] = b.S_left;
     ga.S[1] = b.S_right;
     ga.wta[0] = b.dstar;
@@ -437,8 +453,6 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ga.W = W;
     ga.H = H;
     ga.n = ctx->n;
-    ga.mulh_prior = (uint32_t)(p.alpha_den - p.alpha_num);
-    ga.mulh_noprior = (uint32_t)(p.blend_mode ? p.alpha_den : p.alpha_den - p.alpha_num);
     ga.prior_cost = p.prior_cost;
     ga.huber_k = p.huber_k;
     ga.q1s = (uint32_t)(p.alpha_num * p.q1);
@@ -596,8 +610,6 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (t.dright && ctx->need_right && cp(t.dright, b.dright, px * 2) != hipSuccess)
         return SLDF_EDEVICE;
     if (cp(t.rho, b.rho, px * 2) != hipSuccess || cp(t.features, b.x0, px * 16) != hipSuccess)
-        return SLDF_EDEVICE;
-    if (t.prior && launch_narrow_prior(b.prior, (int16_t*)t.prior, (int64_t)px, s) != hipSuccess)
         return SLDF_EDEVICE;
     return SLDF_OK;
 }

@@ -9,16 +9,24 @@ namespace sldf {
 // Workspace segments of one context (segment-major: every segment holds all
 // batch frames back to back with the stated frame stride, in elements).
 // Census rows are padded by D codes on both sides so that every matching
-// pixel x -+ d of a disparity range lies inside the allocation; census_l and
-// census_r point at pixel (0, 0) of frame 0 (pad included before it) and
-// pixel (x, y) of frame f sits at f * census_fstride + y * census_pitch + x.
+// pixel x -+ d of a disparity range lies inside the allocation, and one guard
+// row lies before frame 0 and after the last frame (rows -1 and H of every
+// frame are inside the allocation); census_l and census_r point at pixel
+// (0, 0) of frame 0 (pad included before it) and pixel (x, y) of frame f sits
+// at f * census_fstride + y * census_pitch + x.  Pads and guard rows are
+// never written: the passes read them only where the cost is masked.
 struct Buffers {
     uint32_t* census_l;
     uint32_t* census_r;
     int32_t census_pitch;     // W + 2 D
     int64_t census_fstride;   // H * census_pitch
-    int32_t* prior;       // [F][H][W] prior of the joint cost: D-hat (SDSGM) or D-bar
-                          // (DSGM), widened to 32 bits for the path passes
+    // prior words of the joint cost (see prior_word): the left view's per
+    // frame, [F][H + 2][W + 2] from D-hat (SDSGM) or D-bar (DSGM), and one
+    // [H + 2][W + 2] map shared by all frames of the right view (no prior);
+    // each points at the guard corner (-1, -1) of frame 0
+    uint32_t* pword[2];
+    int32_t pword_pitch;      // W + 2
+    int64_t pword_fstride;    // (H + 2) * (W + 2), left view
     int16_t* dstar;       // [F][H][W]
     int16_t* dright;      // [F][H][W]
     float* dsub;          // [F][H][W]
@@ -48,6 +56,42 @@ struct CensusArgs {
     int32_t W, H, cw, ch;
 };
 
+// Prior word of a pixel: what the path passes need of the prior e_p of the
+// joint cost (Eq. 4), precomputed once per pixel so that a step does not
+// derive it per lane.  Bits 0-15: the census weight of the pixel's cost,
+// (den - num) with a prior, (den - num) or den (blend mode 1) without, and 0
+// on the guard ring around each map (the virtual positions before a line
+// start read the ring and get cost 0).  Bits 16-31: byte offset, in the LDS
+// prior-term table (build_pattern), of the first of the four packed entries
+// lane 0 (disparities 0..7) reads; lane g reads 16 g bytes further.  The
+// table holds P[k] = num * q(|k - D|) for k in [0, 2 D + 16) as pairs
+// (P[2 i], P[2 i + 1]) at word i and pairs (P[2 i + 1], P[2 i + 2]) at word
+// D + 8 + i, then a run of D / 2 zero words for pixels without prior.
+__host__ __device__ constexpr int pattern_words(int D) { return 2 * (D + 8) + D / 2; }
+__host__ __device__ inline uint32_t prior_word(int e, int D, uint32_t w_prior,
+                                               uint32_t w_noprior)
+{
+    // lane 0, disparity 0: entry k = 0 - e + D; odd entries sit in the second half
+    if ((unsigned)e >= (unsigned)D) return ((uint32_t)(2 * (D + 8)) * 4u << 16) | w_noprior;
+    const int k = D - e;
+    const uint32_t word = (uint32_t)(k >> 1) + ((k & 1) ? (uint32_t)(D + 8) : 0u);
+    return (word * 4u << 16) | w_prior;
+}
+__host__ __device__ constexpr uint32_t guard_word(int D)
+{
+    return (uint32_t)(2 * (D + 8)) * 4u << 16;
+}
+
+// Destination of the prior words of the left view (and the debug tap of
+// the prior disparities of frame 0).
+struct PriorOut {
+    uint32_t* words;            // guard corner (-1, -1) of frame 0
+    int32_t pitch;              // W + 2
+    int64_t fstride;
+    uint32_t w_prior, w_noprior;
+    int16_t* tap;               // [H][W] e_p of frame 0, or null
+};
+
 struct SemiArgs {
     const uint32_t* census_l;
     const uint32_t* census_r;
@@ -56,8 +100,7 @@ struct SemiArgs {
     const int16_t* lidar;
     int32_t lidar_pitch;
     int64_t lidar_fstride;
-    int32_t* out;
-    int64_t px_stride;
+    PriorOut out;
     int32_t W, H, D, n, ts, rs;
 };
 
@@ -66,9 +109,9 @@ struct SgmArgs {
     const uint32_t* cmatch[2];  // matching-view census per view
     int32_t census_pitch;
     int64_t census_fstride;
-    const int32_t* prior;       // left-view prior (D-hat / D-bar), 32-bit
-    int32_t prior_pitch;
-    int64_t prior_fstride;
+    const uint32_t* pword[2];   // prior words per view, guard corner of frame 0
+    int32_t pword_pitch;
+    int64_t pword_fstride[2];   // the right view's map is shared (stride 0)
     uint16_t* S[2];             // aggregated cost per view
     int16_t* wta[2];            // integer WTA output per view (d*, d')
     float* dsub;                // left-view subpixel output
@@ -78,8 +121,6 @@ struct SgmArgs {
     int32_t n;                  // census bits (cost where the match leaves)
     int32_t dx, dy;             // path step r
     int32_t nlines;
-    uint32_t mulh_prior;        // (den - num)
-    uint32_t mulh_noprior;      // (den - num) or den (blend mode 1)
     uint32_t q1s, q2s;          // num * Q1, num * Q2
     int32_t prior_cost;         // 0 DDC, 1 quadratic, 2 Huber (table in build_pattern)
     int32_t huber_k;
@@ -214,12 +255,13 @@ enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2, kSingle = 3 };
 
 hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s);
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s);
-// D-bar int16 (caller's pitch) -> 32-bit prior map (dense rows of W)
-hipError_t launch_widen_prior(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
-                              int32_t* out, int32_t W, int32_t H, int64_t out_fstride,
+// D-bar int16 (caller's pitch) -> prior words (DSGM)
+hipError_t launch_prior_words(const int16_t* in, int32_t in_pitch, int64_t in_fstride,
+                              const PriorOut& out, int32_t W, int32_t H, int32_t D,
                               int nframes, hipStream_t s);
-// 32-bit prior map of one frame -> int16 (debug tap)
-hipError_t launch_narrow_prior(const int32_t* in, int16_t* out, int64_t n, hipStream_t s);
+// guard rings of the left-view maps and the right view's shared map
+hipError_t launch_prior_guards(const PriorOut& out, uint32_t* right, uint32_t w_right,
+                               int32_t W, int32_t H, int32_t D, int nframes, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
 // two opposite directions (dx, dy) and (-dx, -dy) in one launch

@@ -52,17 +52,24 @@ def test_workspace_size_plan():
     W, H, D = 1242, 375, 128
     px, cells = W * H, W * H * D
     census = 2 * (W + 2 * D) * H * 4            # padded census rows, both views
-    # prior (i32), d*, d' (i16), dsub (f32), S left + right (u16), LiDAR row masks
-    # (D/32 words), rho (u16), cost features (2 u32), surrogate inputs (8 bf16)
+    # prior words (u32, one-pixel guard ring), d*, d' (i16), dsub (f32), S left +
+    # right (u16), LiDAR row masks (D/32 words), rho (u16), cost features
+    # (2 u32), surrogate inputs (8 bf16)
     # paired-direction checkpoints: every 8 pixels of each line, D u16 per
     # checkpoint, both views; the largest pair is the diagonal one
     segs = lambda n: (n + 7) // 8
     ck = max(H * segs(W), W * segs(H), (W + H - 1) * segs(min(W, H))) * D * 2 * 2
-    exact = (census + px * (4 + 2 + 2 + 4) + 2 * cells * 2 + ck +
-             px * (D // 32 * 4 + 2 + 8 + 16))
-    assert exact <= n1 < exact + 16 * 256
+    pw = (W + 2) * (H + 2) * 4
+    per_frame = (census + pw + px * (2 + 2 + 4) + 2 * cells * 2 + ck +
+                 px * (D // 32 * 4 + 2 + 8 + 16))
+    # once per context: a guard row before and after the census of each view,
+    # the right view's prior words
+    fixed = 2 * 2 * (W + 2 * D) * 4 + pw
+    exact = per_frame + fixed
+    assert exact <= n1 < exact + 18 * 256
     p.batch = 4
-    assert 4 * exact <= sldf.workspace_size(p) < 4 * exact + 16 * 256
+    exact4 = 4 * per_frame + fixed
+    assert exact4 <= sldf.workspace_size(p) < exact4 + 18 * 256
     p = sldf.default_params(check_mode=2)      # no right-view pass: one S volume
     assert sldf.workspace_size(p) < n1 - cells
 
