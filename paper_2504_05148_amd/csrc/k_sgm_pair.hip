@@ -144,7 +144,15 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                     if (a.store_sum) store_s(la, o, St);
                     const int t = u - pad;
                     const uint32_t px = (uint32_t)((y0 + t * a.dy) * a.W + x0 + t * a.dx);
-                    wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px);
+                    // the segment cost slot j is free now: it takes S(p, .)
+                    // so that the WTA reads the neighbours of d* from LDS
+                    const uint16_t* simg = nullptr;
+                    if (VIEW == 0) {
+                        cw[j * 64] = u32x4{St[0], St[1], St[2], St[3]};
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        simg = reinterpret_cast<const uint16_t*>(cw + j * 64 - g);
+                    }
+                    wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px, simg);
                 }
             }
             if (kLoadS) Sin[j] = load_s(la, sat(u - kSeg));

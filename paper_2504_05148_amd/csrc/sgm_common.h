@@ -317,10 +317,12 @@ __device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t 
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
 // of (S, d), ties -> smallest d) and the parabola fit through S(d*-1),
 // S(d*), S(d*+1); the owning lane writes d* (and for the left view the
-// subpixel disparity and the learned-check cost features).
+// subpixel disparity and the learned-check cost features).  simg, when not
+// null, is the line's S(p, .) as D u16 in LDS (written by the group before
+// the call), from which the owner reads the two neighbours of d*.
 template <int G, int VIEW>
 __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4], int d0,
-                                         size_t px)
+                                         size_t px, const uint16_t* simg = nullptr)
 {
     constexpr int D = G * 8;
     uint32_t best = 0xffffffffu;
@@ -332,8 +334,8 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
     }
     best = group_min<G>(best);
     const int db = (int)(best & 511u);
-    const uint32_t spv = dpp<kWaveShr1>(St[3]);
-    const uint32_t snx = dpp<kWaveShl1>(St[0]);
+    const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[3]);
+    const uint32_t snx = simg ? 0u : dpp<kWaveShl1>(St[0]);
     // learned-check cost feature: second minimum of S over |d - d*| >= 2
     uint32_t second = 0xffffu;
     if (VIEW == 0 && a.feat) {
@@ -349,23 +351,27 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
     if (db >= d0 && db < d0 + 8) {
         a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
-            // cells d0-1 .. d0+8 of S
-            uint32_t c[10];
-            c[0] = spv >> 16;
+            uint32_t A = 0, B = best >> 9, Cc = 0;   // S(d*) is the minimum itself
+            if (simg) {
+                A = db > 0 ? simg[db - 1] : 0u;
+                Cc = db < D - 1 ? simg[db + 1] : 0u;
+            } else {
+                // cells d0-1 .. d0+8 of S
+                uint32_t c[10];
+                c[0] = spv >> 16;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                c[1 + 2 * i] = St[i] & 0xffffu;
-                c[2 + 2 * i] = St[i] >> 16;
-            }
-            c[9] = snx & 0xffffu;
-            const int j = db - d0 + 1;
-            uint32_t A = 0, B = 0, Cc = 0;
+                for (int i = 0; i < 4; ++i) {
+                    c[1 + 2 * i] = St[i] & 0xffffu;
+                    c[2 + 2 * i] = St[i] >> 16;
+                }
+                c[9] = snx & 0xffffu;
+                const int j = db - d0 + 1;
 #pragma unroll
-            for (int k = 1; k <= 8; ++k) {
-                if (k == j) {
-                    A = c[k - 1];
-                    B = c[k];
-                    Cc = c[k + 1];
+                for (int k = 1; k <= 8; ++k) {
+                    if (k == j) {
+                        A = c[k - 1];
+                        Cc = c[k + 1];
+                    }
                 }
             }
             float v = (float)db;
