@@ -33,6 +33,8 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
     constexpr bool kStoreS = MODE == kFirst || MODE == kMiddle;
     constexpr int kRing = ring_depth<MODE>();
+    // slot j % kRing of a segment must be slot j % kRing of the next one
+    static_assert(kSeg % kRing == 0, "the ring depth must divide the segment length");
     int x0, y0, len;
     line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
