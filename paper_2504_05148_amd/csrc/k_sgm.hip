@@ -1,8 +1,9 @@
 // SGM path aggregation, one direction per launch, with the joint census + DDC
 // cost fused in (Sec. III Eq. 2, Sec. IV-A Eq. 4) and the winner-takes-all +
 // subpixel step fused into the last direction (Eq. 3).  Used for the
-// one-path debug mode; the 4- and 8-path sets run the paired kernel
-// (k_sgm_pair.hip), which handles two opposite directions per launch.
+// one-path debug mode and, two directions per launch, for the split schedule
+// of small batches; larger batches run the paired kernel (k_sgm_pair.hip),
+// which handles two opposite directions per line.
 //
 // Every line of the direction is an independent recurrence owned by G = D / 8
 // lanes (see sgm_common.h).  The aggregated sum S = sum_r L_r is kept as u16
@@ -16,14 +17,14 @@ namespace sldf {
 
 template <int G, int MODE, int VIEW>
 __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, int line,
-                                         int g, int frame)
+                                         int g, int frame, int dx, int dy, uint16_t* S)
 {
     constexpr int D = G * 8;
     constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
     int x0, y0, len;
-    line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
+    line_start(line, a.W, a.H, dx, dy, x0, y0, len);
     const int d0 = g * 8;
-    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0);
+    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0, dx, dy, S);
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
     uint32_t L[4] = {0, 0, 0, 0};   // zero state: the first step yields L = C
@@ -31,7 +32,7 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     uint32_t m = 0;
     auto step = [&](const StepIn& in, const u32x4& s_in, int t) {
         uint32_t C[4];
-        cost8<D, VIEW>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x0 + t * a.dx, d0, C);
+        cost8<D, VIEW>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x0 + t * dx, d0, C);
         rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
         const PixOff o = la.at(t);
         if (MODE == kFirst) {
@@ -50,7 +51,7 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
                 for (int i = 0; i < 4; ++i) St[i] = L[i];
             }
             if (a.store_sum) store_s(la, o, St);
-            const uint32_t px = (uint32_t)((y0 + t * a.dy) * a.W + x0 + t * a.dx);
+            const uint32_t px = (uint32_t)((y0 + t * dy) * a.W + x0 + t * dx);
             wta_emit<G, VIEW>(a, St, d0, (size_t)frame * a.px_stride + px);
         }
     };
@@ -78,6 +79,62 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     }
 }
 
+// One direction of the split schedule (MODE kFirst: S = L_r, kMiddle:
+// S += L_r).  As in the paired pass, the line is padded at its start to a
+// whole number of kRing positions with virtual positions that read the
+// guard position before the line start (cost 0: the state stays zero and
+// their S update is a no-op on pixel 0, stored before pixel 0's own), so
+// every step loads, computes and stores unconditionally and the inputs and
+// S of kRing positions ahead are in flight.
+template <int G, int MODE, int VIEW>
+__device__ __forceinline__ void run_line_split(const SgmArgs& a, const uint32_t* pat, int line,
+                                               int g, int frame, int dx, int dy, uint16_t* S)
+{
+    constexpr int D = G * 8;
+    constexpr bool kLoadS = MODE == kMiddle;
+    constexpr int kRing = 8;
+    int x0, y0, len;
+    line_start(line, a.W, a.H, dx, dy, x0, y0, len);
+    const int d0 = g * 8;
+    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0, dx, dy, S);
+    const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
+    const bool gfirst = g == 0, glast = g == G - 1;
+    const char* patl = reinterpret_cast<const char*>(pat) + 2 * d0;
+    const int pad = (len + kRing - 1) / kRing * kRing - len;
+    const int nu = len + pad;
+    uint32_t L[4] = {0, 0, 0, 0};
+    uint32_t m = 0;
+    Edge edge;
+    StepIn R[kRing];
+    u32x4 SR[kRing];
+    auto load = [&](int i, int u) {
+        load_pixel<VIEW>(la, la.at(max(u - pad, -1)), R[i]);
+        if (kLoadS) SR[i] = load_s(la, la.at(min(max(u - pad, 0), len - 1)));
+    };
+    // issued in slot order (the loop's waits assume slot 0 is the oldest)
+#pragma unroll
+    for (int i = 0; i < kRing; ++i) {
+        load(i, i);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int u0 = 0; u0 < nu; u0 += kRing) {
+#pragma unroll
+        for (int i = 0; i < kRing; ++i) {
+            const int u = u0 + i;
+            uint32_t C[4];
+            cost8<D, VIEW>(a, patl, R[i], x0 + (u - pad) * dx, d0, C);
+            rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
+            uint32_t v[4] = {L[0], L[1], L[2], L[3]};
+            if (kLoadS) {
+                v[0] = pk_add(v[0], SR[i].x); v[1] = pk_add(v[1], SR[i].y);
+                v[2] = pk_add(v[2], SR[i].z); v[3] = pk_add(v[3], SR[i].w);
+            }
+            store_s(la, la.at(max(u - pad, 0)), v);
+            load(i, min(u + kRing, nu - 1));
+        }
+    }
+}
+
 template <int G, int MODE>
 __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
 {
@@ -99,10 +156,20 @@ __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
     const int g = threadIdx.x % G;
     const int line = (logical - fv * a.blocks_per_fv) * (256 / G) + threadIdx.x / G;
     if (line >= a.nlines) return;
-    if (view == 0)
-        run_line<G, MODE, 0>(a, pat, line, g, frame);
-    else
-        run_line<G, MODE, 1>(a, pat, line, g, frame);
+    // blockIdx.y = 1 (split schedule): the opposite direction, into S2
+    const int sg = blockIdx.y ? -1 : 1;
+    uint16_t* S = blockIdx.y ? a.S2[view] : a.S[view];
+    if (MODE == kFirst || MODE == kMiddle) {
+        if (view == 0)
+            run_line_split<G, MODE, 0>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
+        else
+            run_line_split<G, MODE, 1>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
+    } else {
+        if (view == 0)
+            run_line<G, MODE, 0>(a, pat, line, g, frame, a.dx, a.dy, S);
+        else
+            run_line<G, MODE, 1>(a, pat, line, g, frame, a.dx, a.dy, S);
+    }
 }
 
 template <int G>
@@ -116,8 +183,8 @@ static void launch_g(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
     }
 }
 
-hipError_t launch_sgm_dir(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
-                          hipStream_t s)
+static hipError_t launch_dir(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
+                             int ndirs, hipStream_t s)
 {
     const int G = D / 8;
     const int lines_per_block = 256 / G;
@@ -126,10 +193,75 @@ hipError_t launch_sgm_dir(const SgmArgs& a0, int D, int mode, int nviews, int nf
     a.nviews = nviews;
     a.n_fv = nviews * nframes;
     const int64_t nb = (int64_t)a.blocks_per_fv * a.n_fv;
-    dim3 grid((unsigned)((nb + kXcds - 1) / kXcds * kXcds));
+    dim3 grid((unsigned)((nb + kXcds - 1) / kXcds * kXcds), ndirs);
     if (G == 8) launch_g<8>(a, mode, grid, s);
     else if (G == 16) launch_g<16>(a, mode, grid, s);
     else launch_g<32>(a, mode, grid, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+                          hipStream_t s)
+{
+    return launch_dir(a, D, mode, nviews, nframes, 1, s);
+}
+
+// Split schedule (small batches): the two directions of a pair run as
+// independent lines, r into S and -r into S2, so a line is one pass of
+// its length instead of three (forward, recompute, backward) and the two
+// run side by side; S + S2 is taken by sgm_wta_kernel after the last pair.
+hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+                           hipStream_t s)
+{
+    return launch_dir(a, D, mode, nviews, nframes, 2, s);
+}
+
+// Winner-takes-all (+ subpixel, cost features) on S + S2: G lanes per pixel,
+// each with its 8 disparities; the pixel's summed costs are staged in LDS
+// for the parabola neighbours.  With store_sum the sum is written back to S
+// (the cost-sum tap).
+template <int G>
+__global__ __launch_bounds__(256) void sgm_wta_kernel(SgmArgs a, int64_t npx_fv)
+{
+    constexpr int D = G * 8;
+    __shared__ u32x4 simg[256];
+    const int64_t q = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;   // pixel-view
+    const int g = threadIdx.x % G;
+    const int fv = (int)(q / npx_fv);
+    if (fv >= a.n_fv) return;
+    const int view = a.view_base + fv % a.nviews, frame = fv / a.nviews;
+    if (a.gate && a.gate[frame] <= a.gate_limit) return;
+    const int64_t p = q - (int64_t)fv * npx_fv;
+    const size_t off = (size_t)frame * a.S_stride + (size_t)p * D + 8 * g;
+    const u32x4 s1 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.S[view] + off));
+    const u32x4 s2 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(a.S2[view] + off));
+    const uint32_t St[4] = {pk_add(s1.x, s2.x), pk_add(s1.y, s2.y), pk_add(s1.z, s2.z),
+                            pk_add(s1.w, s2.w)};
+    const size_t px = (size_t)frame * a.px_stride + (size_t)p;
+    if (view == 0) {
+        if (a.store_sum)
+            *reinterpret_cast<u32x4*>(a.S[0] + off) = u32x4{St[0], St[1], St[2], St[3]};
+        simg[threadIdx.x] = u32x4{St[0], St[1], St[2], St[3]};
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        wta_emit<G, 0>(a, St, 8 * g, px,
+                       reinterpret_cast<const uint16_t*>(&simg[threadIdx.x - g]));
+    } else {
+        wta_emit<G, 1>(a, St, 8 * g, px);
+    }
+}
+
+hipError_t launch_sgm_wta(const SgmArgs& a0, int D, int nviews, int nframes, hipStream_t s)
+{
+    const int G = D / 8;
+    SgmArgs a = a0;
+    a.nviews = nviews;
+    a.n_fv = nviews * nframes;
+    const int64_t npx = (int64_t)a.W * a.H;
+    const int64_t nb = (npx * a.n_fv + 256 / G - 1) / (256 / G);
+    dim3 grid((unsigned)nb);
+    if (G == 8) hipLaunchKernelGGL(sgm_wta_kernel<8>, grid, dim3(256), 0, s, a, npx);
+    else if (G == 16) hipLaunchKernelGGL(sgm_wta_kernel<16>, grid, dim3(256), 0, s, a, npx);
+    else hipLaunchKernelGGL(sgm_wta_kernel<32>, grid, dim3(256), 0, s, a, npx);
     return hipGetLastError();
 }
 

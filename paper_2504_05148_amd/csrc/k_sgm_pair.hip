@@ -30,15 +30,19 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                                          int line, int g, int frame, int fv)
 {
     constexpr int D = G * 8;
-    constexpr bool kLoadS = MODE == kMiddle || MODE == kLast;
-    constexpr bool kStoreS = MODE == kFirst || MODE == kMiddle;
+    constexpr bool kLoadS2 = MODE == kMiddle2;
+    constexpr bool kLoadS = MODE == kMiddle || MODE == kLast || kLoadS2;
+    constexpr bool kStoreS = MODE == kFirst || MODE == kMiddle || kLoadS2;
     constexpr int kRing = ring_depth<MODE>();
     // slot j % kRing of a segment must be slot j % kRing of the next one
     static_assert(kSeg % kRing == 0, "the ring depth must divide the segment length");
     int x0, y0, len;
     line_start(line, a.W, a.H, a.dx, a.dy, x0, y0, len);
     const int d0 = g * 8;
-    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0);
+    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0, a.dx, a.dy, a.S[VIEW]);
+    // kMiddle2: the second term S2 of the split first pass, folded into S here
+    const LineAddr la2 = kLoadS2 ? line_addr<D, VIEW>(a, frame, x0, y0, d0, a.dx, a.dy, a.S2[VIEW])
+                                 : la;
     uint32_t* __restrict__ ck =
         a.ckpt + (((size_t)fv * a.nlines + line) * a.ckpt_segs * G + g) * 4;
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
@@ -87,10 +91,12 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
     // the backward direction -r then walks the segment in reverse and adds
     // L_r + L_-r into S (or takes the WTA).  While segment s is walked, the
     // inputs, checkpoint and S of segment s - 1 are already in flight.
-    u32x4 Sin[kSeg];
+    u32x4 Sin[kSeg], Sin2[kLoadS2 ? kSeg : 1];
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j)
+    for (int j = 0; j < kSeg; ++j) {
         Sin[j] = kLoadS ? load_s(la, sat((nseg - 1) * kSeg + j)) : u32x4{0u, 0u, 0u, 0u};
+        if (kLoadS2) Sin2[j] = load_s(la2, sat((nseg - 1) * kSeg + j));
+    }
     // forward state entering a segment: its checkpoint (zero for the first
     // segment), with the group minimum; prepared one iteration ahead
     uint32_t Ln[4], mn;
@@ -137,6 +143,10 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                 St[0] = pk_add(St[0], Sin[j].x); St[1] = pk_add(St[1], Sin[j].y);
                 St[2] = pk_add(St[2], Sin[j].z); St[3] = pk_add(St[3], Sin[j].w);
             }
+            if (kLoadS2) {
+                St[0] = pk_add(St[0], Sin2[j].x); St[1] = pk_add(St[1], Sin2[j].y);
+                St[2] = pk_add(St[2], Sin2[j].z); St[3] = pk_add(St[3], Sin2[j].w);
+            }
             const int u = u0 + j;
             if (u >= pad) {
                 const PixOff o = la.at(u - pad);
@@ -158,6 +168,7 @@ __device__ __forceinline__ void run_pair(const SgmArgs& a, const uint32_t* pat, 
                 }
             }
             if (kLoadS) Sin[j] = load_s(la, sat(u - kSeg));
+            if (kLoadS2) Sin2[j] = load_s(la2, sat(u - kSeg));
         }
         enter(cin, s == 1);
     }
@@ -198,6 +209,7 @@ static void launch_pg(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
     switch (mode) {
     case kFirst: hipLaunchKernelGGL((sgm_pair_kernel<G, kFirst>), grid, dim3(256), 0, s, a); break;
     case kMiddle: hipLaunchKernelGGL((sgm_pair_kernel<G, kMiddle>), grid, dim3(256), 0, s, a); break;
+    case kMiddle2: hipLaunchKernelGGL((sgm_pair_kernel<G, kMiddle2>), grid, dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((sgm_pair_kernel<G, kLast>), grid, dim3(256), 0, s, a); break;
     }
 }

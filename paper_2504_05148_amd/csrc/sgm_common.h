@@ -154,10 +154,11 @@ struct LineAddr {
 };
 
 
-// frame and view are uniform over a workgroup, so the bases are too
+// frame and view are uniform over a workgroup, so the bases are too; the
+// line steps by (dx, dy) and its S term is the view's buffer S
 template <int D, int VIEW>
 __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x0, int y0,
-                                              int d0)
+                                              int d0, int dx, int dy, uint16_t* S)
 {
     LineAddr la;
     // census rows are addressed from the padded start of the row before
@@ -167,16 +168,16 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
     la.cbase = uniform_ptr<gcptr>(a.cbase[VIEW] - crow + (int64_t)frame * a.census_fstride);
     la.cmatch = uniform_ptr<gcptr>(a.cmatch[VIEW] - crow + (int64_t)frame * a.census_fstride);
     la.prior = uniform_ptr<gcptr>(a.pword[VIEW] + (int64_t)frame * a.pword_fstride[VIEW]);
-    la.S = uniform_ptr<gptr>(a.S[VIEW] + (int64_t)frame * a.S_stride);
+    la.S = uniform_ptr<gptr>(S + (int64_t)frame * a.S_stride);
     la.oc0 = (uint32_t)((y0 + 1) * a.census_pitch + x0 + D) * 4u;
     // matching pixels: x - d (left base, descending) or x + d (right base)
     // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
     la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + 7) * 4u : la.oc0 + (uint32_t)d0 * 4u;
     la.op0 = (uint32_t)((y0 + 1) * a.pword_pitch + x0 + 1) * 4u;
     la.os0 = ((uint32_t)(y0 * a.W + x0) * D + (uint32_t)d0) * 2u;
-    la.dc = (a.dy * a.census_pitch + a.dx) * 4;
-    la.dp = (a.dy * a.pword_pitch + a.dx) * 4;
-    la.ds = (a.dy * a.W + a.dx) * D * 2;
+    la.dc = (dy * a.census_pitch + dx) * 4;
+    la.dp = (dy * a.pword_pitch + dx) * 4;
+    la.ds = (dy * a.W + dx) * D * 2;
     return la;
 }
 

@@ -71,6 +71,7 @@ sldf_status validate(const sldf_params* p)
          !(p->uncertain_margin >= 0.f)))
         return SLDF_EINVAL;
     if (p->subpixel != 0 && p->subpixel != 1) return SLDF_EINVAL;
+    if (p->schedule < 0 || p->schedule > 2) return SLDF_EINVAL;
     if (p->prior_cost < 0 || p->prior_cost > 2 || p->huber_k < 1 || p->huber_k > 4096)
         return SLDF_EINVAL;
     if (p->batch < 1 || p->batch > 4096) return SLDF_EINVAL;
@@ -126,6 +127,11 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* dsub = seg(F * px * 4);
     void* sl = seg(F * cells * 2);
     void* sr = needs_right(p) ? seg(F * cells * 2) : nullptr;
+    // second cost term of the split schedule (batches of up to kSplitFrames)
+    const size_t Fs = F < (size_t)kSplitFrames ? F : (size_t)kSplitFrames;
+    const bool split = p->num_paths >= 4 && p->schedule != 1;
+    void* s2l = split ? seg(Fs * cells * 2) : nullptr;
+    void* s2r = split && needs_right(p) ? seg(Fs * cells * 2) : nullptr;
     // checkpoints of the paired passes: the largest direction pair in use
     size_t ck_per_fv = 0;
     for (int k = 0; k < (p->num_paths >= 4 ? p->num_paths / 2 : 0); ++k) {
@@ -159,6 +165,8 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->dsub = (float*)dsub;
         b->S_left = (uint16_t*)sl;
         b->S_right = (uint16_t*)sr;
+        b->S2[0] = (uint16_t*)s2l;
+        b->S2[1] = (uint16_t*)s2r;
         b->ckpt = (uint32_t*)ck;
         b->rowbits = (uint32_t*)rb;
         b->rho = (uint16_t*)rho;
@@ -228,6 +236,7 @@ void sldf_params_default(sldf_params* p)
     p->uncertain_margin = 0.5f;
     p->prior_cost = 0;    // DDC
     p->huber_k = 1;
+    p->schedule = 0;      // automatic
 }
 
 sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes)
@@ -477,8 +486,38 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             ctx->launches[stage] += 1;
             return true;
         }
-        // opposite directions in pairs: S is read-modified-written once per pair
         const int npairs = p.num_paths / 2;
+        // small batches: the split schedule.  The horizontal pair (the
+        // longest lines, and the fewest) runs its two directions as separate
+        // line passes, r into S and -r into S2, so one pass of a row's
+        // length is on its critical path instead of three; the next pair
+        // folds S2 into S (8 paths), or both pairs are split and one WTA pass
+        // takes S + S2 (4 paths).  The price is the S2 traffic.
+        const bool split = p.schedule != 1 && n_frames <= kSplitFrames && b.S2[view_base] &&
+                           (nv == 1 || b.S2[view_base + 1]);
+        if (split) {
+            ga.S2[0] = b.S2[0];
+            ga.S2[1] = b.S2[1];
+            for (int k = 0; k < npairs; ++k) {
+                ga.dx = kPairDirs[k][0];
+                ga.dy = kPairDirs[k][1];
+                ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+                hipError_t e2;
+                if (k == 0 || npairs == 2)
+                    e2 = launch_sgm_dual(ga, D, k == 0 ? kFirst : kMiddle, nv, n_frames, s);
+                else
+                    e2 = launch_sgm_pair(ga, D, k == 1 ? kMiddle2 : k == npairs - 1 ? kLast : kMiddle,
+                                         nv, n_frames, s);
+                if (e2 != hipSuccess) return false;
+                ctx->launches[stage] += 1;
+            }
+            if (npairs == 2) {
+                if (launch_sgm_wta(ga, D, nv, n_frames, s) != hipSuccess) return false;
+                ctx->launches[stage] += 1;
+            }
+            return true;
+        }
+        // opposite directions in pairs: S is read-modified-written once per pair
         for (int k = 0; k < npairs; ++k) {
             ga.dx = kPairDirs[k][0];
             ga.dy = kPairDirs[k][1];

@@ -32,6 +32,8 @@ struct Buffers {
     float* dsub;          // [F][H][W]
     uint16_t* S_left;     // [F][H][W][D]
     uint16_t* S_right;    // [F][H][W][D] (only when the stereo check is on)
+    uint16_t* S2[2];      // split schedule (small batches): second cost term per view,
+                          // [min(F, kSplitFrames)][H][W][D]
     uint32_t* ckpt;       // paired-pass checkpoints, [F * views][lines][segs][D / 2] u32
     uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
     uint16_t* rho;        // [F][H][W] LiDAR residual
@@ -113,6 +115,7 @@ struct SgmArgs {
     int32_t pword_pitch;
     int64_t pword_fstride[2];   // the right view's map is shared (stride 0)
     uint16_t* S[2];             // aggregated cost per view
+    uint16_t* S2[2];            // split schedule: the term of the opposite directions
     int16_t* wta[2];            // integer WTA output per view (d*, d')
     float* dsub;                // left-view subpixel output
     int64_t px_stride;
@@ -251,7 +254,9 @@ hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s);
 
-enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2, kSingle = 3 };
+// path pass roles: the first pass stores S, middle ones add into it, the
+// last takes the WTA; kMiddle2 also adds the second term S2 of a split pass
+enum SgmMode { kFirst = 0, kMiddle = 1, kLast = 2, kSingle = 3, kMiddle2 = 4 };
 
 hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s);
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s);
@@ -264,6 +269,13 @@ hipError_t launch_prior_guards(const PriorOut& out, uint32_t* right, uint32_t w_
                                int32_t W, int32_t H, int32_t D, int nframes, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
+// split schedule: direction (dx, dy) into S and (-dx, -dy) into S2, one launch
+hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nframes,
+                           hipStream_t s);
+// split schedule: winner-takes-all (+ subpixel) on S + S2 of every pixel
+hipError_t launch_sgm_wta(const SgmArgs& a, int D, int nviews, int nframes, hipStream_t s);
+// batches of at most this many frames use the split schedule
+constexpr int kSplitFrames = 2;
 // two opposite directions (dx, dy) and (-dx, -dy) in one launch
 hipError_t launch_sgm_pair(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                            hipStream_t s);

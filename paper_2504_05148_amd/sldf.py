@@ -25,7 +25,7 @@ _PARAM_FIELDS = ("struct_size", "width", "height", "max_disp", "census_w", "cens
 
 
 _PARAM_FLOATS = ("fallback_tau", "uncertain_margin")
-_PARAM_TAIL = ("prior_cost", "huber_k")     # int32 fields after the floats
+_PARAM_TAIL = ("prior_cost", "huber_k", "schedule")     # int32 fields after the floats
 
 
 class Params(ctypes.Structure):

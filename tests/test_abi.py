@@ -63,15 +63,20 @@ def test_workspace_size_plan():
     per_frame = (census + pw + px * (2 + 2 + 4) + 2 * cells * 2 + ck +
                  px * (D // 32 * 4 + 2 + 8 + 16))
     # once per context: a guard row before and after the census of each view,
-    # the right view's prior words
+    # the right view's prior words; the split schedule's second cost term
+    # for up to 2 frames, both views
     fixed = 2 * 2 * (W + 2 * D) * 4 + pw
-    exact = per_frame + fixed
-    assert exact <= n1 < exact + 18 * 256
+    split = lambda F: min(F, 2) * 2 * cells * 2
+    exact = per_frame + fixed + split(1)
+    assert exact <= n1 < exact + 20 * 256
     p.batch = 4
-    exact4 = 4 * per_frame + fixed
-    assert exact4 <= sldf.workspace_size(p) < exact4 + 18 * 256
+    exact4 = 4 * per_frame + fixed + split(4)
+    assert exact4 <= sldf.workspace_size(p) < exact4 + 20 * 256
     p = sldf.default_params(check_mode=2)      # no right-view pass: one S volume
     assert sldf.workspace_size(p) < n1 - cells
+    # the paired schedule needs no second cost term
+    p = sldf.default_params(schedule=1)
+    assert n1 - split(1) <= sldf.workspace_size(p) < n1 - split(1) + 20 * 256
 
 
 @pytest.mark.parametrize("field,value,status", [
@@ -90,6 +95,7 @@ def test_workspace_size_plan():
     ("check_impl", 2, sldf.EINVAL),
     ("batch", 0, sldf.EINVAL),
     ("prior_cost", 3, sldf.EINVAL),
+    ("schedule", 3, sldf.EINVAL),
     ("huber_k", 0, sldf.EINVAL),
     ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
 ])

@@ -110,13 +110,20 @@ def assert_parity(g, o, pkw, taps=True):
 SMALL = dict(census_w=5, census_h=5, num_paths=4)
 
 
+# path pass schedules (identical results): 1 = paired directions on one
+# line, 2 = split (each direction its own line pass, then one WTA pass)
+SCHEDULES = [1, 2]
+
+
 @pytest.mark.parametrize("idx", [0, 1])
 @pytest.mark.parametrize("semi", [0, 1])
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
-def test_small_workload(idx, semi, mode):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_small_workload(idx, semi, mode, schedule):
     f = synth.small_frame(idx)
-    pkw = _params(f["W"], f["H"], f["D"], semidense=semi, check_mode=mode, **SMALL)
-    print(f"case small idx={idx} semi={semi} mode={mode}", flush=True)
+    pkw = _params(f["W"], f["H"], f["D"], semidense=semi, check_mode=mode, schedule=schedule,
+                  **SMALL)
+    print(f"case small idx={idx} semi={semi} mode={mode} schedule={schedule}", flush=True)
     assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
 
 
@@ -128,13 +135,16 @@ def test_small_bit_exact_subpixel():
 
 
 def test_paper_scale_frame():
-    """1242 x 375, D = 128, 9x7 census, 8 paths, SDSGM, stereo-LiDAR check."""
+    """1242 x 375, D = 128, 9x7 census, 8 paths, SDSGM, stereo-LiDAR check,
+    under both path pass schedules."""
     f = synth.kitti_frame(0)
     pkw = _params(1242, 375, 128)
-    print("case kitti frame 0", flush=True)
-    g, o = run_gpu(f, pkw), run_oracle(f, pkw)
-    assert_parity(g, o, pkw)
-    assert (g["dsub"].view(np.uint32) == o["dsub"].view(np.uint32)).all()
+    o = run_oracle(f, pkw)
+    for schedule in SCHEDULES:
+        print(f"case kitti frame 0 schedule={schedule}", flush=True)
+        g = run_gpu(f, dict(pkw, schedule=schedule))
+        assert_parity(g, o, pkw)
+        assert (g["dsub"].view(np.uint32) == o["dsub"].view(np.uint32)).all()
 
 
 @pytest.mark.parametrize("prior_cost,huber_k", [(1, 1), (2, 2)])
@@ -149,7 +159,10 @@ def test_paper_scale_alternative_prior_terms(prior_cost, huber_k):
 def test_paper_scale_dsgm():
     f = synth.kitti_frame(1)
     pkw = _params(1242, 375, 128, semidense=0)
-    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+    o = run_oracle(f, pkw)
+    for schedule in SCHEDULES:
+        print(f"case kitti dsgm schedule={schedule}", flush=True)
+        assert_parity(run_gpu(f, dict(pkw, schedule=schedule)), o, pkw)
 
 
 @pytest.mark.parametrize("W,H,D,paths", [(333, 77, 128, 8), (130, 19, 64, 8), (301, 40, 256, 8),
@@ -159,8 +172,10 @@ def test_ragged_shapes(W, H, D, paths):
     spec = synth.robust_spec(W=W, H=H, D=D, density=0.05, lines=16)
     f = synth.make_frame(spec, 3, W * 7 + H)
     pkw = _params(W, H, D, num_paths=paths)
-    print(f"case ragged {W}x{H} D={D} paths={paths}", flush=True)
-    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+    o = run_oracle(f, pkw)
+    for schedule in SCHEDULES:
+        print(f"case ragged {W}x{H} D={D} paths={paths} schedule={schedule}", flush=True)
+        assert_parity(run_gpu(f, dict(pkw, schedule=schedule)), o, pkw)
 
 
 @pytest.mark.parametrize("extra", [
@@ -174,8 +189,10 @@ def test_parameter_variants(extra):
     f = synth.small_frame(4)
     pkw = _params(f["W"], f["H"], f["D"], **SMALL)
     pkw.update(extra)
-    print(f"case variant {extra}", flush=True)
-    assert_parity(run_gpu(f, pkw), run_oracle(f, pkw), pkw)
+    o = run_oracle(f, pkw)
+    for schedule in SCHEDULES:
+        print(f"case variant {extra} schedule={schedule}", flush=True)
+        assert_parity(run_gpu(f, dict(pkw, schedule=schedule)), o, pkw)
 
 
 @pytest.mark.parametrize("density", [0.0, 0.3])
