@@ -113,14 +113,14 @@ typedef struct {
                               t = |d - prior| */
     int32_t huber_k;       /* Huber threshold k >= 1 (prior_cost 2) */
     int32_t schedule;      /* order of the path passes (results identical):
-                              0 = automatic (split for runs of at most 2
-                              frames, paired otherwise); 1 = paired: both
+                              0 = automatic (split for single-frame runs,
+                              paired otherwise); 1 = paired: both
                               directions of a pair on one line, S read and
                               written once per pair; 2 = split: the two
                               directions of a pair as separate lines into two
                               cost terms, then one WTA pass (shortest critical
-                              path, twice the S traffic; runs of more than 2
-                              frames fall back to paired) */
+                              path, more S traffic; runs of more than one
+                              frame fall back to paired) */
 } sldf_params;
 
 /* Optional debug taps: device pointers, any may be NULL.  Written for frame

@@ -127,7 +127,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* dsub = seg(F * px * 4);
     void* sl = seg(F * cells * 2);
     void* sr = needs_right(p) ? seg(F * cells * 2) : nullptr;
-    // second cost term of the split schedule (batches of up to kSplitFrames)
+    // second cost term of the split schedule (runs of up to kSplitFrames frames)
     const size_t Fs = F < (size_t)kSplitFrames ? F : (size_t)kSplitFrames;
     const bool split = p->num_paths >= 4 && p->schedule != 1;
     void* s2l = split ? seg(Fs * cells * 2) : nullptr;
@@ -487,7 +487,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             return true;
         }
         const int npairs = p.num_paths / 2;
-        // small batches: the split schedule.  The horizontal pair (the
+        // single frames: the split schedule.  The horizontal pair (the
         // longest lines, and the fewest) runs its two directions as separate
         // line passes, r into S and -r into S2, so one pass of a row's
         // length is on its critical path instead of three; the next pair

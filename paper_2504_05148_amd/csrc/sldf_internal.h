@@ -32,7 +32,7 @@ struct Buffers {
     float* dsub;          // [F][H][W]
     uint16_t* S_left;     // [F][H][W][D]
     uint16_t* S_right;    // [F][H][W][D] (only when the stereo check is on)
-    uint16_t* S2[2];      // split schedule (small batches): second cost term per view,
+    uint16_t* S2[2];      // split schedule (single frames): second cost term per view,
                           // [min(F, kSplitFrames)][H][W][D]
     uint32_t* ckpt;       // paired-pass checkpoints, [F * views][lines][segs][D / 2] u32
     uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
@@ -274,8 +274,8 @@ hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nf
                            hipStream_t s);
 // split schedule: winner-takes-all (+ subpixel) on S + S2 of every pixel
 hipError_t launch_sgm_wta(const SgmArgs& a, int D, int nviews, int nframes, hipStream_t s);
-// batches of at most this many frames use the split schedule
-constexpr int kSplitFrames = 2;
+// runs of at most this many frames use the split schedule
+constexpr int kSplitFrames = 1;
 // two opposite directions (dx, dy) and (-dx, -dy) in one launch
 hipError_t launch_sgm_pair(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                            hipStream_t s);

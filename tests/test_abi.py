@@ -64,9 +64,9 @@ def test_workspace_size_plan():
                  px * (D // 32 * 4 + 2 + 8 + 16))
     # once per context: a guard row before and after the census of each view,
     # the right view's prior words; the split schedule's second cost term
-    # for up to 2 frames, both views
+    # for one frame, both views
     fixed = 2 * 2 * (W + 2 * D) * 4 + pw
-    split = lambda F: min(F, 2) * 2 * cells * 2
+    split = lambda F: min(F, 1) * 2 * cells * 2
     exact = per_frame + fixed + split(1)
     assert exact <= n1 < exact + 20 * 256
     p.batch = 4
