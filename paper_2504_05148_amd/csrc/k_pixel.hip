@@ -132,13 +132,18 @@ __device__ __forceinline__ void emit_prior(const PriorOut& o, int f, int x, int 
 
 __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
 {
-    __shared__ int16_t tile[kSemiLT][kSemiLT];
-    __shared__ uint32_t cand[kSemiLT * kSemiLT];          // (row << 16) | (col << 8) | d
-    __shared__ uint32_t crow[kSemiT][kSemiMaxD + kSemiT];  // right census of the reachable columns
+    // LDS sized for this D and rs (so that more blocks fit a CU): the right
+    // census of the reachable columns [kSemiT][D + kSemiT], the candidate
+    // list [lt * lt] ((row << 16) | (col << 8) | d), the LiDAR tile [lt][lt]
+    extern __shared__ uint32_t smem[];
     __shared__ int ncand;
     const int frame = blockIdx.z;
     const int16_t* lid = a.lidar + (int64_t)frame * a.lidar_fstride;
     const int rs = a.rs, lt = kSemiT + 2 * rs, D = a.D;
+    const int cp = D + kSemiT;
+    uint32_t* crow = smem;
+    uint32_t* cand = smem + kSemiT * cp;
+    int16_t* tile = reinterpret_cast<int16_t*>(cand + lt * lt);
     const int x0 = blockIdx.x * kSemiT, y0 = blockIdx.y * kSemiT;
     if (threadIdx.x == 0) ncand = 0;
     // all staging loads of a thread are issued before its LDS writes, so
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
         if (i >= lt * lt) break;
         const int r = i / lt, c = i - r * lt;
         const int16_t v = tv[k];
-        tile[r][c] = v;
+        tile[r * lt + c] = v;
         // values outside [0, D) are no candidates (the ABI admits only -1)
         if ((unsigned)v < (unsigned)D) cand[atomicAdd(&ncand, 1)] = (r << 16) | (c << 8) | v;
     }
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     for (int k = 0; k < kRowK; ++k) {
         const int i = threadIdx.x + 256 * k;
         if (i >= kSemiT * cw) break;
-        crow[i / cw][i % cw] = cv[k];
+        crow[(i / cw) * cp + i % cw] = cv[k];
     }
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     auto visit = [&](int d) {
         // matching pixel x - d: staged column tx - d + D - 1 (in [0, cw) for
         // 0 <= d < D)
-        const uint32_t h = x - d >= 0 ? (uint32_t)__builtin_popcount(c ^ crow[ty][tx - d + D - 1])
+        const uint32_t h = x - d >= 0 ? (uint32_t)__builtin_popcount(c ^ crow[ty * cp + tx - d + D - 1])
                                       : (uint32_t)a.n;
         const uint32_t key = (h << 16) | (uint32_t)d;
         best = key < best ? key : best;
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(256) void semidense_kernel(SemiArgs a)
     } else {
         for (int r = 0; r < w; ++r)
             for (int q = 0; q < w; ++q) {
-                const int d = tile[ty + r][tx + q];
+                const int d = tile[(ty + r) * lt + tx + q];
                 if ((unsigned)d < (unsigned)D) visit(d);
             }
     }
@@ -283,7 +288,9 @@ hipError_t launch_prior_guards(const PriorOut& out, uint32_t* right, uint32_t w_
 hipError_t launch_semidense(const SemiArgs& a, int nframes, hipStream_t s)
 {
     dim3 grid((a.W + kSemiT - 1) / kSemiT, (a.H + kSemiT - 1) / kSemiT, nframes);
-    hipLaunchKernelGGL(semidense_kernel, grid, dim3(256), 0, s, a);
+    const int lt = kSemiT + 2 * a.rs;
+    const size_t lds = ((size_t)kSemiT * (a.D + kSemiT) + (size_t)lt * lt) * 4 + (size_t)lt * lt * 2;
+    hipLaunchKernelGGL(semidense_kernel, grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

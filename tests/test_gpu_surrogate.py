@@ -128,12 +128,17 @@ def test_train_step_deterministic_and_descends():
     assert losses[-1] < 0.8 * losses[0], losses
 
 
-def test_learned_run_matches_definition():
+# both path pass schedules (1 paired, 2 split), 4 and 8 paths
+SCHED_PATHS = [(1, 4), (2, 4), (1, 8), (2, 8)]
+
+
+@pytest.mark.parametrize("schedule,paths", SCHED_PATHS)
+def test_learned_run_matches_definition(schedule, paths):
     """sldf_run with check_impl = 1 (fallback off) equals
     (CNN logit > 0) or (rho <= Tc) on the features of the same frame."""
     f = synth.small_frame(3)
     pkw = dict(width=f["W"], height=f["H"], max_disp=f["D"], census_w=5, census_h=5,
-               num_paths=4)
+               num_paths=paths, schedule=schedule)
     base = _features(f, pkw)
     _, wbits, b = _params_bits(4)
     wt = torch.from_numpy(wbits.view(np.int16)).cuda()
@@ -152,12 +157,13 @@ def test_learned_run_matches_definition():
     assert (disp[~valid.bool()] == -1).all()
 
 
-def test_fallback_forced_equals_plain_check():
+@pytest.mark.parametrize("schedule,paths", SCHED_PATHS)
+def test_fallback_forced_equals_plain_check(schedule, paths):
     """tau = 0 with a margin no logit reaches: every frame falls back to the
     right-view pass and the plain check, bit-exactly."""
     f = synth.small_frame(4)
     pkw = dict(width=f["W"], height=f["H"], max_disp=f["D"], census_w=5, census_h=5,
-               num_paths=4)
+               num_paths=paths, schedule=schedule)
     base = _features(f, pkw)
     _, wbits, b = _params_bits(5)
     wt = torch.from_numpy(wbits.view(np.int16)).cuda()
