@@ -30,10 +30,10 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     uint32_t L[4] = {0, 0, 0, 0};   // zero state: the first step yields L = C
     Edge edge;
     uint32_t m = 0;
-    auto step = [&](const StepIn& in, const u32x4& s_in, int t) {
+    auto step = [&](const StepIn<4>& in, const u32x4& s_in, int t) {
         uint32_t C[4];
-        cost8<D, VIEW>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x0 + t * dx, d0, C);
-        rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
+        cost_lane<D, VIEW>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x0 + t * dx, d0, C);
+        rec_lane<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
         const PixOff o = la.at(t);
         if (MODE == kFirst) {
             store_s(la, o, L);
@@ -57,9 +57,9 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
     };
     // three steps in flight: the loads of step t+3 are issued once step t
     // has consumed its buffer
-    StepIn b0, b1, b2;
+    StepIn<4> b0, b1, b2;
     u32x4 s0 = {}, s1 = {}, s2 = {};
-    auto load = [&](StepIn& b, u32x4& sv, int t) {
+    auto load = [&](StepIn<4>& b, u32x4& sv, int t) {
         const PixOff o = la.at(t);
         load_pixel<VIEW>(la, o, b);
         if (kLoadS) sv = load_s(la, o);
@@ -86,30 +86,30 @@ __device__ __forceinline__ void run_line(const SgmArgs& a, const uint32_t* pat, 
 // their S update is a no-op on pixel 0, stored before pixel 0's own), so
 // every step loads, computes and stores unconditionally and the inputs and
 // S of kRing positions ahead are in flight.
-template <int G, int MODE, int VIEW>
+template <int G, int MODE, int VIEW, int NR>
 __device__ __forceinline__ void run_line_split(const SgmArgs& a, const uint32_t* pat, int line,
                                                int g, int frame, int dx, int dy, uint16_t* S)
 {
-    constexpr int D = G * 8;
+    constexpr int K = 2 * NR, D = G * K;   // K disparities per lane
     constexpr bool kLoadS = MODE == kMiddle;
     constexpr int kRing = 8;
     int x0, y0, len;
     line_start(line, a.W, a.H, dx, dy, x0, y0, len);
-    const int d0 = g * 8;
-    const LineAddr la = line_addr<D, VIEW>(a, frame, x0, y0, d0, dx, dy, S);
+    const int d0 = g * K;
+    const LineAddr la = line_addr<D, VIEW, K>(a, frame, x0, y0, d0, dx, dy, S);
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
     const char* patl = reinterpret_cast<const char*>(pat) + 2 * d0;
     const int pad = (len + kRing - 1) / kRing * kRing - len;
     const int nu = len + pad;
-    uint32_t L[4] = {0, 0, 0, 0};
+    uint32_t L[NR] = {};
     uint32_t m = 0;
     Edge edge;
-    StepIn R[kRing];
-    u32x4 SR[kRing];
+    StepIn<NR> R[kRing];
+    vecT<NR> SR[kRing];
     auto load = [&](int i, int u) {
         load_pixel<VIEW>(la, la.at(max(u - pad, -1)), R[i]);
-        if (kLoadS) SR[i] = load_s(la, la.at(min(max(u - pad, 0), len - 1)));
+        if (kLoadS) SR[i] = load_s<NR>(la, la.at(min(max(u - pad, 0), len - 1)));
     };
     // issued in slot order (the loop's waits assume slot 0 is the oldest)
 #pragma unroll
@@ -121,24 +121,22 @@ __device__ __forceinline__ void run_line_split(const SgmArgs& a, const uint32_t*
 #pragma unroll
         for (int i = 0; i < kRing; ++i) {
             const int u = u0 + i;
-            uint32_t C[4];
-            cost8<D, VIEW>(a, patl, R[i], x0 + (u - pad) * dx, d0, C);
-            rec8<G>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
-            uint32_t v[4] = {L[0], L[1], L[2], L[3]};
-            if (kLoadS) {
-                v[0] = pk_add(v[0], SR[i].x); v[1] = pk_add(v[1], SR[i].y);
-                v[2] = pk_add(v[2], SR[i].z); v[3] = pk_add(v[3], SR[i].w);
-            }
-            store_s(la, la.at(max(u - pad, 0)), v);
+            uint32_t C[NR];
+            cost_lane<D, VIEW, NR>(a, patl, R[i], x0 + (u - pad) * dx, d0, C);
+            rec_lane<G, NR>(L, m, C, p1x2, p2x2, gfirst, glast, edge);
+            uint32_t v[NR];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) v[q] = kLoadS ? pk_add(L[q], SR[i][q]) : L[q];
+            store_s<NR>(la, la.at(max(u - pad, 0)), v);
             load(i, min(u + kRing, nu - 1));
         }
     }
 }
 
-template <int G, int MODE>
+template <int G, int MODE, int NR>
 __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
 {
-    constexpr int D = G * 8;
+    constexpr int D = G * 2 * NR;
     __shared__ uint32_t pat[pattern_words(D)];
     build_pattern<D>(a, pat);
     __syncthreads();
@@ -159,11 +157,11 @@ __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
     // blockIdx.y = 1 (split schedule): the opposite direction, into S2
     const int sg = blockIdx.y ? -1 : 1;
     uint16_t* S = blockIdx.y ? a.S2[view] : a.S[view];
-    if (MODE == kFirst || MODE == kMiddle) {
+    if constexpr (MODE == kFirst || MODE == kMiddle) {
         if (view == 0)
-            run_line_split<G, MODE, 0>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
+            run_line_split<G, MODE, 0, NR>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
         else
-            run_line_split<G, MODE, 1>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
+            run_line_split<G, MODE, 1, NR>(a, pat, line, g, frame, sg * a.dx, sg * a.dy, S);
     } else {
         if (view == 0)
             run_line<G, MODE, 0>(a, pat, line, g, frame, a.dx, a.dy, S);
@@ -176,17 +174,28 @@ template <int G>
 static void launch_g(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
 {
     switch (mode) {
-    case kFirst: hipLaunchKernelGGL((sgm_dir_kernel<G, kFirst>), grid, dim3(256), 0, s, a); break;
-    case kMiddle: hipLaunchKernelGGL((sgm_dir_kernel<G, kMiddle>), grid, dim3(256), 0, s, a); break;
-    case kLast: hipLaunchKernelGGL((sgm_dir_kernel<G, kLast>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((sgm_dir_kernel<G, kSingle>), grid, dim3(256), 0, s, a); break;
+    case kFirst: hipLaunchKernelGGL((sgm_dir_kernel<G, kFirst, 4>), grid, dim3(256), 0, s, a); break;
+    case kMiddle: hipLaunchKernelGGL((sgm_dir_kernel<G, kMiddle, 4>), grid, dim3(256), 0, s, a); break;
+    case kLast: hipLaunchKernelGGL((sgm_dir_kernel<G, kLast, 4>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((sgm_dir_kernel<G, kSingle, 4>), grid, dim3(256), 0, s, a); break;
     }
 }
 
-static hipError_t launch_dir(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
-                             int ndirs, hipStream_t s)
+// four disparities per lane: the split passes of single-frame runs
+template <int G>
+static void launch_g2(const SgmArgs& a, int mode, dim3 grid, hipStream_t s)
 {
-    const int G = D / 8;
+    if (mode == kFirst)
+        hipLaunchKernelGGL((sgm_dir_kernel<G, kFirst, 2>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((sgm_dir_kernel<G, kMiddle, 2>), grid, dim3(256), 0, s, a);
+}
+
+static hipError_t launch_dir(const SgmArgs& a0, int D, int mode, int nviews, int nframes,
+                             int ndirs, hipStream_t s, int k = 8)
+{
+    if (k == 4 && (D > 128 || (mode != kFirst && mode != kMiddle))) return hipErrorInvalidValue;
+    const int G = D / k;
     const int lines_per_block = 256 / G;
     SgmArgs a = a0;
     a.blocks_per_fv = (a.nlines + lines_per_block - 1) / lines_per_block;
@@ -194,9 +203,16 @@ static hipError_t launch_dir(const SgmArgs& a0, int D, int mode, int nviews, int
     a.n_fv = nviews * nframes;
     const int64_t nb = (int64_t)a.blocks_per_fv * a.n_fv;
     dim3 grid((unsigned)((nb + kXcds - 1) / kXcds * kXcds), ndirs);
-    if (G == 8) launch_g<8>(a, mode, grid, s);
-    else if (G == 16) launch_g<16>(a, mode, grid, s);
-    else launch_g<32>(a, mode, grid, s);
+    if (k == 4) {
+        if (G == 16) launch_g2<16>(a, mode, grid, s);
+        else launch_g2<32>(a, mode, grid, s);
+    } else if (G == 8) {
+        launch_g<8>(a, mode, grid, s);
+    } else if (G == 16) {
+        launch_g<16>(a, mode, grid, s);
+    } else {
+        launch_g<32>(a, mode, grid, s);
+    }
     return hipGetLastError();
 }
 
@@ -211,9 +227,9 @@ hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nfr
 // its length instead of three (forward, recompute, backward) and the two
 // run side by side; S + S2 is taken by sgm_wta_kernel after the last pair.
 hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nframes,
-                           hipStream_t s)
+                           hipStream_t s, int k)
 {
-    return launch_dir(a, D, mode, nviews, nframes, 2, s);
+    return launch_dir(a, D, mode, nviews, nframes, 2, s, k);
 }
 
 // Winner-takes-all (+ subpixel, cost features) on S + S2: G lanes per pixel,

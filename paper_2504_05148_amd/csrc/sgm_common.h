@@ -3,8 +3,12 @@
 // reductions, line geometry, per-step loads, the fused cost, one recurrence
 // step and the winner-takes-all + parabola emit.
 //
-// A line of a path direction is owned by G = D / 8 lanes of a wavefront;
-// lane g holds disparities [8g, 8g + 8) as four packed 2 x u16 registers.
+// A line of a path direction is owned by G = D / K lanes of a wavefront;
+// lane g holds disparities [K g, K g + K) as NR = K / 2 packed 2 x u16
+// registers.  K = 8 (four registers) is the throughput layout; K = 4 (two
+// registers, twice the lanes per line) halves the work of a lane per step
+// and serves single frames, whose few lines leave the SIMDs idle otherwise.
+// Memory layouts (S, census, prior words) do not depend on K.
 #pragma once
 
 #include "sldf_internal.h"
@@ -14,6 +18,21 @@ namespace sldf {
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// NR packed registers as one vector (16 or 8 bytes per lane)
+template <int NR> struct VecT;
+template <> struct VecT<4> { typedef u32x4 type; };
+template <> struct VecT<2> { typedef u32x2 type; };
+template <int NR> using vecT = typename VecT<NR>::type;
+template <int NR>
+__device__ __forceinline__ vecT<NR> pack_v(const uint32_t v[NR])
+{
+    vecT<NR> x;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) x[i] = v[i];
+    return x;
+}
 
 __device__ __forceinline__ u16x2 v2(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ uint32_t u1(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
@@ -118,9 +137,10 @@ __device__ __forceinline__ P uniform_ptr(const void* p)
 }
 
 // Inputs of one step (one pixel of the line) for one lane.
+template <int NR>
 struct StepIn {
     uint32_t cb;        // census of the base pixel
-    u32x4a4 m0, m1;     // census of 8 consecutive matching pixels
+    u32x4a4 m[NR / 2];  // census of K = 2 NR consecutive matching pixels
     uint32_t w;         // prior word of the pixel (sldf_internal.h)
 };
 
@@ -155,8 +175,9 @@ struct LineAddr {
 
 
 // frame and view are uniform over a workgroup, so the bases are too; the
-// line steps by (dx, dy) and its S term is the view's buffer S
-template <int D, int VIEW>
+// line steps by (dx, dy) and its S term is the view's buffer S; the lane
+// owns disparities d0 .. d0 + K - 1
+template <int D, int VIEW, int K = 8>
 __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x0, int y0,
                                               int d0, int dx, int dy, uint16_t* S)
 {
@@ -171,8 +192,8 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
     la.S = uniform_ptr<gptr>(S + (int64_t)frame * a.S_stride);
     la.oc0 = (uint32_t)((y0 + 1) * a.census_pitch + x0 + D) * 4u;
     // matching pixels: x - d (left base, descending) or x + d (right base)
-    // for d = d0 .. d0+7; the census pad keeps both runs inside the buffer
-    la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + 7) * 4u : la.oc0 + (uint32_t)d0 * 4u;
+    // for d = d0 .. d0+K-1; the census pad keeps both runs inside the buffer
+    la.om0 = VIEW == 0 ? la.oc0 - (uint32_t)(d0 + K - 1) * 4u : la.oc0 + (uint32_t)d0 * 4u;
     la.op0 = (uint32_t)((y0 + 1) * a.pword_pitch + x0 + 1) * 4u;
     la.os0 = ((uint32_t)(y0 * a.W + x0) * D + (uint32_t)d0) * 2u;
     la.dc = (dy * a.census_pitch + dx) * 4;
@@ -181,138 +202,152 @@ __device__ __forceinline__ LineAddr line_addr(const SgmArgs& a, int frame, int x
     return la;
 }
 
-template <int VIEW>
-__device__ __forceinline__ void load_pixel(const LineAddr& la, const PixOff& o, StepIn& st)
+template <int VIEW, int NR>
+__device__ __forceinline__ void load_pixel(const LineAddr& la, const PixOff& o, StepIn<NR>& st)
 {
     typedef __attribute__((address_space(1))) const uint32_t* gu32;
     typedef __attribute__((address_space(1))) const u32x4a4* gu32x4;
     st.cb = *reinterpret_cast<gu32>(la.cbase + o.oc);
     const gcptr pm = la.cmatch + o.om;
-    st.m0 = *reinterpret_cast<gu32x4>(pm);
-    st.m1 = *reinterpret_cast<gu32x4>(pm + 16);
+#pragma unroll
+    for (int i = 0; i < NR / 2; ++i) st.m[i] = *reinterpret_cast<gu32x4>(pm + 16 * i);
     st.w = *reinterpret_cast<gu32>(la.prior + o.op);
 }
 
 // S streams through once per pass: non-temporal loads / stores, so it does not
-// evict the census rows that neighbouring lines re-read from L2.
-__device__ __forceinline__ u32x4 load_s(const LineAddr& la, const PixOff& o)
+// evict the census rows that neighbouring lines re-read from L2.  The lane's
+// NR registers are its K cells of the pixel's D (contiguous, 2 NR x 2 bytes).
+template <int NR = 4>
+__device__ __forceinline__ vecT<NR> load_s(const LineAddr& la, const PixOff& o)
 {
-    typedef __attribute__((address_space(1))) const u32x4* gcv;
+    typedef __attribute__((address_space(1))) const vecT<NR>* gcv;
     return __builtin_nontemporal_load(reinterpret_cast<gcv>(la.S + o.os));
 }
-__device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, const uint32_t v[4])
+template <int NR = 4>
+__device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, const uint32_t v[NR])
 {
-    typedef __attribute__((address_space(1))) u32x4* gv;
-    __builtin_nontemporal_store(u32x4{v[0], v[1], v[2], v[3]}, reinterpret_cast<gv>(la.S + o.os));
+    typedef __attribute__((address_space(1))) vecT<NR>* gv;
+    __builtin_nontemporal_store(pack_v<NR>(v), reinterpret_cast<gv>(la.S + o.os));
 }
 
-// Joint cost C'(p, d) for d = d0 .. d0+7 (Eq. 4 scaled by the alpha
-// denominator): w H + num DDC with H = popcount of the census xor (n where
-// the matching pixel leaves the image), the weight w and the DDC table entry
-// from the pixel's prior word (sldf_internal.h).  The prior term is read from
-// the LDS table at patl (the lane's first entry, pattern + 2 d0 bytes) plus
-// the word's offset; the right view has no prior term.  On the guard ring the
-// weight is 0 and the entry a zero run, so the virtual positions before a
-// line start cost 0: from a zero state L = 0, m = 0 such a step leaves the
-// state at zero, and the first real pixel then yields L = C as Eq. 2 starts
-// a path.
-template <int D, int VIEW>
-__device__ __forceinline__ void cost8(const SgmArgs& a, const char* patl, const StepIn& in,
-                                      int x, int d0, uint32_t C[4])
+// Joint cost C'(p, d) for the lane's d = d0 .. d0+K-1 (Eq. 4 scaled by the
+// alpha denominator): w H + num DDC with H = popcount of the census xor (n
+// where the matching pixel leaves the image), the weight w and the DDC table
+// entry from the pixel's prior word (sldf_internal.h).  The prior term is
+// read from the LDS table at patl (the lane's first entry, pattern + 2 d0
+// bytes) plus the word's offset; the right view has no prior term.  On the
+// guard ring the weight is 0 and the entry a zero run, so the virtual
+// positions before a line start cost 0: from a zero state L = 0, m = 0 such a
+// step leaves the state at zero, and the first real pixel then yields L = C
+// as Eq. 2 starts a path.
+template <int D, int VIEW, int NR = 4>
+__device__ __forceinline__ void cost_lane(const SgmArgs& a, const char* patl,
+                                          const StepIn<NR>& in, int x, int d0, uint32_t C[NR])
 {
-    uint32_t mc[8];
-    if (VIEW == 0) {
-        mc[0] = in.m1.w; mc[1] = in.m1.z; mc[2] = in.m1.y; mc[3] = in.m1.x;
-        mc[4] = in.m0.w; mc[5] = in.m0.z; mc[6] = in.m0.y; mc[7] = in.m0.x;
-    } else {
-        mc[0] = in.m0.x; mc[1] = in.m0.y; mc[2] = in.m0.z; mc[3] = in.m0.w;
-        mc[4] = in.m1.x; mc[5] = in.m1.y; mc[6] = in.m1.z; mc[7] = in.m1.w;
-    }
-    uint32_t h[8];
+    constexpr int K = 2 * NR;
+    // in.m holds the K matching codes in ascending address order: x - d
+    // descends with d for the left base, x + d ascends for the right base
+    uint32_t mc[K];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
-    if (VIEW == 0 ? x < d0 + 7 : x + d0 + 7 >= a.W) {
+    for (int j = 0; j < K; ++j) {
+        const int e = VIEW == 0 ? K - 1 - j : j;
+        mc[j] = in.m[e / 4][e % 4];
+    }
+    uint32_t h[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
+    if (VIEW == 0 ? x < d0 + K - 1 : x + d0 + K - 1 >= a.W) {
         // distance of the lane's first matching pixel from the image edge;
-        // opaque, so that the compiler derives the eight tests here instead
-        // of carrying eight induction variables through every step
+        // opaque, so that the compiler derives the K tests here instead of
+        // carrying K induction variables through every step
         int k = VIEW == 0 ? x - d0 : a.W - 1 - x - d0;
         asm volatile("" : "+v"(k));
 #pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = k < j ? (uint32_t)a.n : h[j];
+        for (int j = 0; j < K; ++j) h[j] = k < j ? (uint32_t)a.n : h[j];
     }
     // the weight (low half of the word) multiplies both halves
     const u16x2 wt = __builtin_shufflevector(v2(in.w), v2(in.w), 0, 0);
     if (VIEW == 0) {
         const uint32_t* p = reinterpret_cast<const uint32_t*>(patl + (in.w >> 16));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt + v2(p[i]));
+        for (int i = 0; i < NR; ++i)
+            C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt + v2(p[i]));
     } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt);
+        for (int i = 0; i < NR; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt);
     }
 }
 
-// Minimum of the lane's 8 cells, in both halves of the result.
-__device__ __forceinline__ uint32_t lane_min2(const uint32_t L[4])
+// Minimum of the lane's K cells, in both halves of the result.
+template <int NR = 4>
+__device__ __forceinline__ uint32_t lane_min(const uint32_t L[NR])
 {
-    // t = min(L0, L1, L2) per half; u adds L3 and the other half of t; the
-    // last minimum with the halves swapped covers all eight cells
-    const f16x2 t = __builtin_bit_cast(f16x2, pk_min3(L[0], L[1], L[2]));
-    const f16x2 l3 = __builtin_bit_cast(f16x2, L[3]);
-    const f16x2 u = __builtin_elementwise_minimum(__builtin_elementwise_minimum(t, l3),
-                                                  __builtin_shufflevector(t, t, 1, 0));
-    return __builtin_bit_cast(uint32_t,
-                              __builtin_elementwise_minimum(u, __builtin_shufflevector(u, u, 1, 0)));
+    if (NR == 4) {
+        // t = min(L0, L1, L2) per half; u adds L3 and the other half of t; the
+        // last minimum with the halves swapped covers all eight cells
+        const f16x2 t = __builtin_bit_cast(f16x2, pk_min3(L[0], L[1], L[2]));
+        const f16x2 l3 = __builtin_bit_cast(f16x2, L[NR - 1]);
+        const f16x2 u = __builtin_elementwise_minimum(__builtin_elementwise_minimum(t, l3),
+                                                      __builtin_shufflevector(t, t, 1, 0));
+        return __builtin_bit_cast(
+            uint32_t, __builtin_elementwise_minimum(u, __builtin_shufflevector(u, u, 1, 0)));
+    } else {
+        // t = min(L0, L1, L0 swapped), then with L1 swapped: all four cells
+        const f16x2 l0 = __builtin_bit_cast(f16x2, L[0]), l1 = __builtin_bit_cast(f16x2, L[1]);
+        const f16x2 t = __builtin_elementwise_minimum(__builtin_elementwise_minimum(l0, l1),
+                                                      __builtin_shufflevector(l0, l0, 1, 0));
+        return __builtin_bit_cast(
+            uint32_t, __builtin_elementwise_minimum(t, __builtin_shufflevector(l1, l1, 1, 0)));
+    }
 }
 
-// One step of Eq. 2 on the lane's 8 disparities.  L holds L_r(p - r, .) on
+// One step of Eq. 2 on the lane's K disparities.  L holds L_r(p - r, .) on
 // entry and L_r(p, .) on exit; m is the group minimum of L_r(p - r, .) on
 // entry and of L_r(p, .) on exit, held in both u16 halves.  A path starts
 // from L = 0, m = 0: the first step then yields L = C.
-// Neighbour exchange registers of the recurrence at D = 128 (a group is one
-// DPP row): a row shift leaves the lane at the row end unwritten, so a
+// Neighbour exchange registers of the recurrence when a group is one DPP
+// row (16 lanes): a row shift leaves the lane at the row end unwritten, so a
 // register that starts as 0xffffffff keeps that value there for good and can
 // serve every step of every chain.
 struct Edge {
     uint32_t pv = 0xffffffffu, nx = 0xffffffffu;
 };
 
-template <int G>
-__device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t C[4],
-                                     uint32_t p1x2, uint32_t p2x2, bool gfirst, bool glast,
-                                     Edge& edge)
+template <int G, int NR = 4>
+__device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint32_t C[NR],
+                                         uint32_t p1x2, uint32_t p2x2, bool gfirst, bool glast,
+                                         Edge& edge)
 {
-    // neighbour cells d0-1 (hi half of pv) and d0+8 (lo half of nx); at the
+    // neighbour cells d0-1 (hi half of pv) and d0+K (lo half of nx); at the
     // ends of the disparity range the term is left out of the minimum
     uint32_t pv, nx;
     if (G == 16) {
         // lanes at the row ends read 0xffff, which never wins the neighbour
         // minimum (the other neighbour is in range)
-        edge.pv = __builtin_amdgcn_update_dpp(edge.pv, L[3], kRowShr1, 0xf, 0xf, false);
+        edge.pv = __builtin_amdgcn_update_dpp(edge.pv, L[NR - 1], kRowShr1, 0xf, 0xf, false);
         edge.nx = __builtin_amdgcn_update_dpp(edge.nx, L[0], kRowShl1, 0xf, 0xf, false);
         pv = edge.pv;
         nx = edge.nx;
     } else {
-        pv = dpp<kWaveShr1>(L[3]);
+        pv = dpp<kWaveShr1>(L[NR - 1]);
         nx = dpp<kWaveShl1>(L[0]);
         // reuse the cell itself, already a candidate of the minimum
         pv = gfirst ? (L[0] << 16) : pv;
-        nx = glast ? (L[3] >> 16) : nx;
+        nx = glast ? (L[NR - 1] >> 16) : nx;
     }
-    uint32_t Dm[5];
+    uint32_t Dm[NR + 1];
     Dm[0] = __builtin_amdgcn_alignbit(L[0], pv, 16);
-    Dm[1] = __builtin_amdgcn_alignbit(L[1], L[0], 16);
-    Dm[2] = __builtin_amdgcn_alignbit(L[2], L[1], 16);
-    Dm[3] = __builtin_amdgcn_alignbit(L[3], L[2], 16);
-    Dm[4] = __builtin_amdgcn_alignbit(nx, L[3], 16);
+#pragma unroll
+    for (int i = 1; i < NR; ++i) Dm[i] = __builtin_amdgcn_alignbit(L[i], L[i - 1], 16);
+    Dm[NR] = __builtin_amdgcn_alignbit(nx, L[NR - 1], 16);
     const uint32_t mp2 = pk_add(m, p2x2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NR; ++i) {
         uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
         uint32_t best = pk_min3(L[i], nb, mp2);
         L[i] = pk_add(best, pk_sub(C[i], m));
     }
-    m = group_min<G>(lane_min2(L));
+    m = group_min<G>(lane_min<NR>(L));
 }
 
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
@@ -321,27 +356,27 @@ __device__ __forceinline__ void rec8(uint32_t L[4], uint32_t& m, const uint32_t 
 // subpixel disparity and the learned-check cost features).  simg, when not
 // null, is the line's S(p, .) as D u16 in LDS (written by the group before
 // the call), from which the owner reads the two neighbours of d*.
-template <int G, int VIEW>
-__device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4], int d0,
+template <int G, int VIEW, int NR = 4>
+__device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR], int d0,
                                          size_t px, const uint16_t* simg = nullptr)
 {
-    constexpr int D = G * 8;
+    constexpr int K = 2 * NR, D = G * K;
     uint32_t best = 0xffffffffu;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NR; ++i) {
         uint32_t k0 = ((St[i] & 0xffffu) << 9) | (uint32_t)(d0 + 2 * i);
         uint32_t k1 = ((St[i] >> 16) << 9) | (uint32_t)(d0 + 2 * i + 1);
         best = min(best, min(k0, k1));
     }
     best = group_min<G>(best);
     const int db = (int)(best & 511u);
-    const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[3]);
+    const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[NR - 1]);
     const uint32_t snx = simg ? 0u : dpp<kWaveShl1>(St[0]);
     // learned-check cost feature: second minimum of S over |d - d*| >= 2
     uint32_t second = 0xffffu;
     if (VIEW == 0 && a.feat) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NR; ++i) {
             const int d_lo = d0 + 2 * i, d_hi = d_lo + 1;
             const uint32_t s_lo = St[i] & 0xffffu, s_hi = St[i] >> 16;
             second = (d_lo - db >= 2 || db - d_lo >= 2) ? min(second, s_lo) : second;
@@ -349,7 +384,7 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
         }
         second = group_min<G>(second);
     }
-    if (db >= d0 && db < d0 + 8) {
+    if (db >= d0 && db < d0 + K) {
         a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
             uint32_t A = 0, B = best >> 9, Cc = 0;   // S(d*) is the minimum itself
@@ -357,18 +392,18 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[4],
                 A = db > 0 ? simg[db - 1] : 0u;
                 Cc = db < D - 1 ? simg[db + 1] : 0u;
             } else {
-                // cells d0-1 .. d0+8 of S
-                uint32_t c[10];
+                // cells d0-1 .. d0+K of S
+                uint32_t c[K + 2];
                 c[0] = spv >> 16;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
+                for (int i = 0; i < NR; ++i) {
                     c[1 + 2 * i] = St[i] & 0xffffu;
                     c[2 + 2 * i] = St[i] >> 16;
                 }
-                c[9] = snx & 0xffffu;
+                c[K + 1] = snx & 0xffffu;
                 const int j = db - d0 + 1;
 #pragma unroll
-                for (int k = 1; k <= 8; ++k) {
+                for (int k = 1; k <= K; ++k) {
                     if (k == j) {
                         A = c[k - 1];
                         Cc = c[k + 1];

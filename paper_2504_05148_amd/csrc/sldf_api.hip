@@ -498,13 +498,18 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         if (split) {
             ga.S2[0] = b.S2[0];
             ga.S2[1] = b.S2[1];
+            // the split passes take four disparities per lane (twice the
+            // lanes per line: a line step is half the instructions) up to
+            // D = 128; the pairs keep eight (measured: their step time does
+            // not shrink with four)
+            const int kd = D <= 128 ? 4 : 8;
             for (int k = 0; k < npairs; ++k) {
                 ga.dx = kPairDirs[k][0];
                 ga.dy = kPairDirs[k][1];
                 ga.nlines = num_lines(W, H, ga.dx, ga.dy);
                 hipError_t e2;
                 if (k == 0 || npairs == 2)
-                    e2 = launch_sgm_dual(ga, D, k == 0 ? kFirst : kMiddle, nv, n_frames, s);
+                    e2 = launch_sgm_dual(ga, D, k == 0 ? kFirst : kMiddle, nv, n_frames, s, kd);
                 else
                     e2 = launch_sgm_pair(ga, D, k == 1 ? kMiddle2 : k == npairs - 1 ? kLast : kMiddle,
                                          nv, n_frames, s);

@@ -269,9 +269,10 @@ hipError_t launch_prior_guards(const PriorOut& out, uint32_t* right, uint32_t w_
                                int32_t W, int32_t H, int32_t D, int nframes, hipStream_t s);
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s);
-// split schedule: direction (dx, dy) into S and (-dx, -dy) into S2, one launch
+// split schedule: direction (dx, dy) into S and (-dx, -dy) into S2, one
+// launch; k disparities per lane (8, or 4 for D <= 128)
 hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nframes,
-                           hipStream_t s);
+                           hipStream_t s, int k = 8);
 // split schedule: winner-takes-all (+ subpixel) on S + S2 of every pixel
 hipError_t launch_sgm_wta(const SgmArgs& a, int D, int nviews, int nframes, hipStream_t s);
 // runs of at most this many frames use the split schedule
