@@ -38,19 +38,24 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c)
 
 // ---------------------------------------------------------------------------
 // 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out.
-// A block computes 64 pixels of 4 output rows that lie on one dilation
-// lattice (rows y, y + d, y + 2d, y + 3d; wave w takes row w, four 16-px
-// tiles).  Those rows read the 6 input rows y - d .. y + 4d, columns
-// x0 - d .. x0 + 63 + d: they are staged once in LDS (zero outside the
-// image), so the nine taps of every output pixel read LDS instead of
-// fetching each input pixel nine times from the caches.  Blocks go to the
-// XCDs in contiguous ranges, so neighbouring column tiles share the halo
-// through one L2.
+// A block owns TW = 64 TPW output columns of one dilation lattice (the rows
+// r, r + d, r + 2d, ... of a residue r) and walks down up to kConvRowsMax of
+// its rows.  Output row i reads the input rows y - d, y, y + d, so
+// consecutive output rows share two of their three input rows: the input
+// rows (columns x0 - d .. x0 + TW - 1 + d, zero outside the image) pass
+// through a ring of kConvSlots LDS slots, each read from memory once per
+// block, and are fetched kConvAhead rows ahead into registers so that their
+// latency overlaps the matrix work of the rows before.  Wave w computes the
+// 16-pixel tiles w, w + 4, .. of every output row; the weights (A operand)
+// stay in registers for the whole block.  Blocks go to the XCDs in
+// contiguous ranges, so neighbouring column tiles share the halo through one
+// L2.  Every output pixel sums its k-steps in order, whatever the tiling.
 // ---------------------------------------------------------------------------
-constexpr int kConvTileW = 64;
-constexpr int kConvRows = 4;
+constexpr int kConvMaxDil = 29;      // largest dilation (LDS budget of the ring)
+constexpr int kConvSlots = 4;        // three input rows in use, one being filled
+constexpr int kConvAhead = 3;        // input rows in flight in registers
+constexpr int kConvRowsMax = 32;     // output rows per block, at most
 constexpr int kConvMaxLds = 65536;
-constexpr int kConvMaxDil = 29;      // largest dilation whose tile fits the LDS budget
 
 // 16-byte chunk c of pixel q (CIN = 32: 4 chunks) is stored at chunk
 // position c ^ ((q >> 2) & 3): the 16 lanes of one LDS read pass (16
@@ -61,18 +66,19 @@ __device__ __forceinline__ int swz(int q, int c)
     return C16 == 4 ? q * 4 + (c ^ ((q >> 2) & 3)) : q * C16 + c;
 }
 
-template <int CIN, int NMT>
+template <int CIN, int NMT, int TPW>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntx, int qblocks,
-                                                      int nframes)
+                                                      int rows_blk, int nframes)
 {
     constexpr int OC = NMT * 16;                 // padded output channels
     constexpr int KSTEPS = CIN == 32 ? 9 : 3;
     constexpr int C16 = CIN / 8;                 // 16-byte chunks per pixel
+    constexpr int TW = 64 * TPW;                 // output columns per block
     constexpr int PPASS = 256 / C16;             // pixels staged per pass
-    constexpr int PASSES = (kConvTileW + 2 * kConvMaxDil + PPASS - 1) / PPASS;
-    extern __shared__ uint4 xin[];               // [kConvRows + 2][tw][C16], swizzled
+    constexpr int PASSES = (TW + 2 * kConvMaxDil + PPASS - 1) / PPASS;
+    extern __shared__ uint4 xin[];               // [kConvSlots][tw][C16], swizzled
     const int d = a.dil;
-    const int tw = kConvTileW + 2 * d;
+    const int tw = TW + 2 * d;
     // block -> (frame, lattice residue r, lattice block qb, column tile tx)
     const int nb = gridDim.x;
     const int b = blockIdx.x;
@@ -80,122 +86,167 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntx, int q
     const int per_frame = ntx * d * qblocks;
     const int frame = logical / per_frame;
     if (frame >= nframes) return;
-    int rem = logical - frame * per_frame;
+    const int rem = logical - frame * per_frame;
     const int yb = rem / ntx, tx = rem - yb * ntx;
     const int r = yb / qblocks, qb = yb - r * qblocks;
-    const int x0 = tx * kConvTileW;
+    const int x0 = tx * TW;
+    const int nrows = min(rows_blk, (a.H - r + d - 1) / d - qb * rows_blk);
+    if (nrows <= 0) return;                      // uniform over the block
     const uint16_t* x = a.x + (int64_t)frame * a.px_stride * CIN;
+    const int ybase = r + d * (qb * rows_blk - 1);   // input row k is ybase + d k
 
-    // stage the input tile: all loads are issued before the LDS writes
-    // (clamped addresses, zero where outside the image)
-    {
-        const int c = threadIdx.x % C16, pxo = threadIdx.x / C16;
-        uint4 v[kConvRows + 2][PASSES];
+    // input row k (0 .. nrows + 1) into registers; rows past the block's
+    // last one repeat it (cache hits, never used), rows outside the image
+    // load a clamped row and are stored as zeros
+    const int c = threadIdx.x % C16, pxo = threadIdx.x / C16;
+    auto load_row = [&](int k, uint4(&v)[PASSES]) {
+        const int sy = ybase + d * min(k, nrows + 1);
+        const int syc = min(max(sy, 0), a.H - 1);
 #pragma unroll
-        for (int row = 0; row < kConvRows + 2; ++row) {
-            const int sy = r + d * (kConvRows * qb + row - 1);
-            const int syc = min(max(sy, 0), a.H - 1);
-#pragma unroll
-            for (int ps = 0; ps < PASSES; ++ps) {
-                const int sx = x0 - d + ps * PPASS + pxo;
-                const int sxc = min(max(sx, 0), a.W - 1);
-                v[row][ps] = *reinterpret_cast<const uint4*>(
-                    x + ((int64_t)syc * a.W + sxc) * CIN + 8 * c);
-            }
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int sx = x0 - d + ps * PPASS + pxo;
+            const int sxc = min(max(sx, 0), a.W - 1);
+            v[ps] = *reinterpret_cast<const uint4*>(x + ((int64_t)syc * a.W + sxc) * CIN + 8 * c);
         }
+    };
+    auto store_row = [&](int k, const uint4(&v)[PASSES]) {
+        const int sy = ybase + d * k;
+        const bool rin = sy >= 0 && sy < a.H;
+        uint4* slot = xin + (k % kConvSlots) * tw * C16;
 #pragma unroll
-        for (int row = 0; row < kConvRows + 2; ++row) {
-            const int sy = r + d * (kConvRows * qb + row - 1);
-#pragma unroll
-            for (int ps = 0; ps < PASSES; ++ps) {
-                const int px = ps * PPASS + pxo;
-                const int sx = x0 - d + px;
-                const bool in = sy >= 0 && sy < a.H && sx >= 0 && sx < a.W;
-                if (px < tw) xin[swz<C16>(row * tw + px, c)] = in ? v[row][ps] : make_uint4(0, 0, 0, 0);
-            }
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int px = ps * PPASS + pxo;
+            const int sx = x0 - d + px;
+            const bool in = rin && sx >= 0 && sx < a.W;
+            if (px < tw) slot[swz<C16>(px, c)] = in ? v[ps] : make_uint4(0, 0, 0, 0);
         }
-    }
-    __syncthreads();
+    };
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane & 15, g = lane >> 4;
-    const int y = r + d * (kConvRows * qb + wave);
-    if (y >= a.H) return;
-    // the four 16-pixel tiles of the wave share each tap's weights (A
-    // operand, read from the cached weight array); every accumulator sums the
-    // taps in order
-    f32x4 acc[4][NMT];
-#pragma unroll
-    for (int xt = 0; xt < 4; ++xt)
-#pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) acc[xt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // weights: A operand of every k-step and output-channel tile
+    uint4 av[KSTEPS][NMT];
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
         const int tap = CIN == 32 ? ks : 4 * ks + g;
         const int ch0 = CIN == 32 ? 8 * g : 0;
-        uint4 av[NMT];
 #pragma unroll
         for (int mt = 0; mt < NMT; ++mt)
-            av[mt] = tap < 9 ? *reinterpret_cast<const uint4*>(a.w + (tap * OC + 16 * mt + j) * CIN + ch0)
-                             : make_uint4(0, 0, 0, 0);
-        const int ky = tap / 3, kx = tap % 3;
-#pragma unroll
-        for (int xt = 0; xt < 4; ++xt) {
-            uint4 bv = make_uint4(0, 0, 0, 0);
-            if (tap < 9)
-                bv = xin[swz<C16>((wave + ky) * tw + xt * 16 + j + kx * d, CIN == 32 ? g : 0)];
-#pragma unroll
-            for (int mt = 0; mt < NMT; ++mt) acc[xt][mt] = mfma16(av[mt], bv, acc[xt][mt]);
-        }
+            av[ks][mt] = tap < 9 ? *reinterpret_cast<const uint4*>(a.w + (tap * OC + 16 * mt + j) * CIN + ch0)
+                                 : make_uint4(0, 0, 0, 0);
     }
+    // bias of the lane's output channels, held for the whole block (a load
+    // inside the row loop would wait for every input row in flight)
+    float bias[NMT][4];
 #pragma unroll
-    for (int xt = 0; xt < 4; ++xt) {
-        const int px = x0 + xt * 16 + j;
-        if (px >= a.W) continue;
-        const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
-        // lane holds pixel j, output channels 16 mt + 4 g + e
+    for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
-        for (int mt = 0; mt < NMT; ++mt) {
-            const int oc0 = 16 * mt + 4 * g;
-            float v[4];
+        for (int e = 0; e < 4; ++e) {
+            const int oc = 16 * mt + 4 * g + e;
+            bias[mt][e] = a.bias && oc < a.cout ? a.bias[oc] : 0.f;
+        }
+    {
+        uint4 v[3][PASSES];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[e] = acc[xt][mt][e] + (a.bias && oc0 + e < a.cout ? a.bias[oc0 + e] : 0.f);
-                if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
+        for (int k = 0; k < 3; ++k) load_row(k, v[k]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) store_row(k, v[k]);
+    }
+    uint4 q[kConvAhead][PASSES];
+#pragma unroll
+    for (int k = 0; k < kConvAhead; ++k) load_row(3 + k, q[k]);
+    __syncthreads();
+
+    // output row i: input rows i, i + 1, i + 2 are in their slots; the slot
+    // of row i + 3 held row i - 1, whose readers all passed the last barrier
+    for (int i0 = 0; i0 < nrows; i0 += kConvAhead) {
+#pragma unroll
+        for (int jj = 0; jj < kConvAhead; ++jj) {
+            const int i = i0 + jj;
+            store_row(i + 3, q[jj]);
+            load_row(i + 3 + kConvAhead, q[jj]);
+            f32x4 acc[TPW][NMT];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                for (int mt = 0; mt < NMT; ++mt) acc[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KSTEPS; ++ks) {
+                const int tap = CIN == 32 ? ks : 4 * ks + g;
+                const int ky = tap / 3, kx = tap % 3;
+                const uint4* slot = xin + ((i + ky) % kConvSlots) * tw * C16;
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) {
+                    const int xt = wave + 4 * t;
+                    uint4 bv = make_uint4(0, 0, 0, 0);
+                    if (tap < 9) bv = slot[swz<C16>(xt * 16 + j + kx * d, CIN == 32 ? g : 0)];
+#pragma unroll
+                    for (int mt = 0; mt < NMT; ++mt) acc[t][mt] = mfma16(av[ks][mt], bv, acc[t][mt]);
+                }
             }
-            if (a.gate) {
-                const uint2 gv = *reinterpret_cast<const uint2*>(a.gate + p * 32 + oc0);
-                const uint16_t gs[4] = {(uint16_t)(gv.x & 0xffff), (uint16_t)(gv.x >> 16),
-                                        (uint16_t)(gv.y & 0xffff), (uint16_t)(gv.y >> 16)};
+            // rows past nrows (the last group's padding) are computed but not stored
+            const int y = r + d * (qb * rows_blk + i);
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    v[e] = (gs[e] != 0 && !(gs[e] & 0x8000)) ? v[e] : 0.f;   // gate > 0
+            for (int t = 0; t < TPW; ++t) {
+                const int px = x0 + (wave + 4 * t) * 16 + j;
+                if (i >= nrows || px >= a.W) continue;
+                const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
+                // lane holds pixel j, output channels 16 mt + 4 g + e
+#pragma unroll
+                for (int mt = 0; mt < NMT; ++mt) {
+                    const int oc0 = 16 * mt + 4 * g;
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        v[e] = acc[t][mt][e] + bias[mt][e];
+                        if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                    }
+                    if (a.gate) {
+                        const uint2 gv = *reinterpret_cast<const uint2*>(a.gate + p * 32 + oc0);
+                        const uint16_t gs[4] = {(uint16_t)(gv.x & 0xffff), (uint16_t)(gv.x >> 16),
+                                                (uint16_t)(gv.y & 0xffff), (uint16_t)(gv.y >> 16)};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            v[e] = (gs[e] != 0 && !(gs[e] & 0x8000)) ? v[e] : 0.f;   // gate > 0
+                    }
+                    if (a.y && oc0 < a.cout) {
+                        uint2 o;
+                        o.x = bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
+                        o.y = bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
+                        *reinterpret_cast<uint2*>(a.y + p * 32 + oc0) = o;
+                    }
+                    if (a.yf && mt == 0 && g == 0) a.yf[p] = v[0];
+                }
             }
-            if (a.y && oc0 < a.cout) {
-                uint2 o;
-                o.x = bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
-                o.y = bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
-                *reinterpret_cast<uint2*>(a.y + p * 32 + oc0) = o;
-            }
-            if (a.yf && mt == 0 && g == 0) a.yf[p] = v[0];
+            __syncthreads();
         }
     }
 }
 
+template <int CIN, int NMT, int TPW>
+static hipError_t launch_conv_tw(const ConvArgs& a, int nframes, hipStream_t s)
+{
+    const int d = a.dil;
+    const size_t lds = (size_t)kConvSlots * (64 * TPW + 2 * d) * CIN * 2;
+    if (d < 1 || d > kConvMaxDil || lds > (size_t)kConvMaxLds) return hipErrorInvalidValue;
+    const int ntx = (a.W + 64 * TPW - 1) / (64 * TPW);
+    const int lattice_rows = (a.H + d - 1) / d;                  // rows per residue, at most
+    const int qblocks = (lattice_rows + kConvRowsMax - 1) / kConvRowsMax;
+    const int rows_blk = (lattice_rows + qblocks - 1) / qblocks;
+    const int64_t nb = (int64_t)ntx * d * qblocks * nframes;
+    dim3 grid((unsigned)((nb + 7) / 8 * 8));
+    hipLaunchKernelGGL((conv3x3_kernel<CIN, NMT, TPW>), grid, dim3(256), lds, s, a, ntx, qblocks,
+                       rows_blk, nframes);
+    return hipGetLastError();
+}
+
+// wide dilations take 128-column tiles (the 2d halo columns are read once
+// per tile, so wider tiles read fewer of them per output pixel)
 template <int CIN, int NMT>
 static hipError_t launch_conv_t(const ConvArgs& a, int nframes, hipStream_t s)
 {
-    const int d = a.dil;
-    const size_t lds = (size_t)(kConvRows + 2) * (kConvTileW + 2 * d) * CIN * 2;
-    if (d < 1 || d > kConvMaxDil || lds > (size_t)kConvMaxLds) return hipErrorInvalidValue;
-    const int ntx = (a.W + kConvTileW - 1) / kConvTileW;
-    const int lattice_rows = (a.H + d - 1) / d;                  // rows per residue, at most
-    const int qblocks = (lattice_rows + kConvRows - 1) / kConvRows;
-    const int64_t nb = (int64_t)ntx * d * qblocks * nframes;
-    dim3 grid((unsigned)((nb + 7) / 8 * 8));
-    hipLaunchKernelGGL((conv3x3_kernel<CIN, NMT>), grid, dim3(256), lds, s, a, ntx, qblocks,
-                       nframes);
-    return hipGetLastError();
+    return a.dil >= 9 ? launch_conv_tw<CIN, NMT, 2>(a, nframes, s)
+                      : launch_conv_tw<CIN, NMT, 1>(a, nframes, s);
 }
 
 hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hipStream_t s)

@@ -44,7 +44,9 @@ def _random_x0(F, H, W, seed):
     return ref.f32_to_bf16_bits(x)
 
 
-@pytest.mark.parametrize("F,H,W", [(1, 37, 70), (2, 64, 129)])
+# sizes: ragged row blocks and column tiles of every dilation; H = 200 gives
+# seven row blocks per lattice at dilation 1
+@pytest.mark.parametrize("F,H,W", [(1, 37, 70), (2, 64, 129), (1, 200, 300)])
 def test_forward_matches_reference(F, H, W):
     """Activations within one bf16 rounding step, logits within a tolerance
     derived from fp32 accumulation of bf16 products."""
