@@ -104,7 +104,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntx, int q
         const int syc = min(max(sy, 0), a.H - 1);
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) {
-            const int sx = x0 - d + ps * PPASS + pxo;
+            // lanes past the tile row (px >= tw) repeat its last pixel, so
+            // their requests merge with that lane's instead of fetching more
+            const int sx = x0 - d + min(ps * PPASS + pxo, tw - 1);
             const int sxc = min(max(sx, 0), a.W - 1);
             v[ps] = *reinterpret_cast<const uint4*>(x + ((int64_t)syc * a.W + sxc) * CIN + 8 * c);
         }
@@ -186,36 +188,49 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntx, int q
             }
             // rows past nrows (the last group's padding) are computed but not stored
             const int y = r + d * (qb * rows_blk + i);
+            const int64_t prow = (int64_t)frame * a.px_stride + (int64_t)y * a.W;
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
-                const int px = x0 + (wave + 4 * t) * 16 + j;
-                if (i >= nrows || px >= a.W) continue;
-                const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
+                const int pxt = x0 + (wave + 4 * t) * 16;    // first pixel of the tile
+                const int px = pxt + j;
+                const bool keep = i < nrows && px < a.W;
+                const int64_t p = prow + px;
                 // lane holds pixel j, output channels 16 mt + 4 g + e
+                float v[NMT][4];
 #pragma unroll
                 for (int mt = 0; mt < NMT; ++mt) {
-                    const int oc0 = 16 * mt + 4 * g;
-                    float v[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        v[e] = acc[t][mt][e] + bias[mt][e];
-                        if (a.relu) v[e] = v[e] > 0.f ? v[e] : 0.f;
+                        v[mt][e] = acc[t][mt][e] + bias[mt][e];
+                        if (a.relu) v[mt][e] = v[mt][e] > 0.f ? v[mt][e] : 0.f;
                     }
-                    if (a.gate) {
-                        const uint2 gv = *reinterpret_cast<const uint2*>(a.gate + p * 32 + oc0);
+                    if (a.gate && keep) {
+                        const uint2 gv = *reinterpret_cast<const uint2*>(a.gate + p * 32 + 16 * mt + 4 * g);
                         const uint16_t gs[4] = {(uint16_t)(gv.x & 0xffff), (uint16_t)(gv.x >> 16),
                                                 (uint16_t)(gv.y & 0xffff), (uint16_t)(gv.y >> 16)};
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            v[e] = (gs[e] != 0 && !(gs[e] & 0x8000)) ? v[e] : 0.f;   // gate > 0
+                            v[mt][e] = (gs[e] != 0 && !(gs[e] & 0x8000)) ? v[mt][e] : 0.f;   // gate > 0
                     }
-                    if (a.y && oc0 < a.cout) {
-                        uint2 o;
-                        o.x = bf16_rne(v[0]) | ((uint32_t)bf16_rne(v[1]) << 16);
-                        o.y = bf16_rne(v[2]) | ((uint32_t)bf16_rne(v[3]) << 16);
-                        *reinterpret_cast<uint2*>(a.y + p * 32 + oc0) = o;
-                    }
-                    if (a.yf && mt == 0 && g == 0) a.yf[p] = v[0];
+                }
+                if (a.yf && g == 0 && keep) a.yf[p] = v[0][0];
+                if (NMT == 2 && a.y) {
+                    // lane (j, g) holds channels 4g..4g+3 (A) and 16+4g..
+                    // 16+4g+3 (B) of pixel j, rows of 16 lanes being g.  One
+                    // swap of the odd rows of A with the even rows of B gives
+                    // row 0 channels 0-7, row 1 16-23, row 2 8-15, row 3
+                    // 24-31: each lane then stores 16 contiguous bytes and a
+                    // wave the tile's 16 whole pixels (1 KB).  Channels at
+                    // or above cout hold bias 0 and zero weights: they are 0.
+                    const uint32_t A0 = bf16_rne(v[0][0]) | ((uint32_t)bf16_rne(v[0][1]) << 16);
+                    const uint32_t A1 = bf16_rne(v[0][2]) | ((uint32_t)bf16_rne(v[0][3]) << 16);
+                    const uint32_t B0 = bf16_rne(v[1][0]) | ((uint32_t)bf16_rne(v[1][1]) << 16);
+                    const uint32_t B1 = bf16_rne(v[1][2]) | ((uint32_t)bf16_rne(v[1][3]) << 16);
+                    const auto s0 = __builtin_amdgcn_permlane16_swap(A0, B0, false, false);
+                    const auto s1 = __builtin_amdgcn_permlane16_swap(A1, B1, false, false);
+                    const uint4 o = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+                    const int chunk = ((g & 1) << 1) | (g >> 1);
+                    if (keep) *reinterpret_cast<uint4*>(a.y + p * 32 + 8 * chunk) = o;
                 }
             }
             __syncthreads();
@@ -253,7 +268,8 @@ hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hi
 {
     if (cin == 32 && cout_pad == 32) return launch_conv_t<32, 2>(a, nframes, s);
     if (cin == 8 && cout_pad == 32) return launch_conv_t<8, 2>(a, nframes, s);
-    if (cin == 32 && cout_pad == 16) return launch_conv_t<32, 1>(a, nframes, s);
+    // 16 padded output channels: channel 0 as fp32 only
+    if (cin == 32 && cout_pad == 16 && !a.y) return launch_conv_t<32, 1>(a, nframes, s);
     return hipErrorInvalidValue;
 }
 

@@ -878,7 +878,7 @@ sldf_status sldf_surrogate_train_step(const uint16_t* x0, const uint8_t* labels,
         cv.cout = 32;
         return launch_conv(cv, gc, 32, F, s) == hipSuccess;
     };
-    // layer 4 (32 -> 1, dilation 8), layer 3, layer 2, layer 1
+    // layer 4 (32 -> 1, dilation 27), layer 3, layer 2, layer 1
     if (!wgrad(a3, 32, dz, 8, kSurDil[3], 16, 1, kSurOffW4, kSurOffB4) ||
         !dgrad(dz, 8, wt4, a3, kSurDil[3], d3) ||
         !wgrad(a2, 32, d3, 32, kSurDil[2], 32, 32, kSurOffW3, kSurOffB3) ||
