@@ -69,6 +69,46 @@ __global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
     }
     __syncthreads();
     uint32_t* out = (view ? a.out_r : a.out_l) + (int64_t)frame * a.out_fstride;
+    if constexpr (CWT != 0) {
+        // a thread takes 4 consecutive pixels of one row (16 threads per
+        // 64-pixel row, 16 rows): bytes x - 4 .. x + 7 of each window row are
+        // three aligned LDS words, and every comparison takes its two bytes
+        // from those registers
+        constexpr int RX = (CWT - 1) / 2, RY = (CHT - 1) / 2, N = (CWT * CHT - 1) / 2;
+        static_assert(RX <= 4, "the register window covers offsets up to 4");
+        const int t = threadIdx.x & 15, ty = threadIdx.x >> 4;
+        const int x = x0 + 4 * t, y = y0 + ty;
+        if (y >= a.H) return;
+        uint32_t R[2 * RY + 1][3];
+#pragma unroll
+        for (int r = 0; r <= 2 * RY; ++r) {
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(&tile[ty + r][12 + 4 * t]);
+            R[r][0] = w[0];
+            R[r][1] = w[1];
+            R[r][2] = w[2];
+        }
+        const bool yin = y >= RY && y < a.H - RY;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            // bit k = [I(p + o_k) > I(p - o_k)], offsets in raster order:
+            // shifted in from the last offset to the first
+            uint32_t code = 0;
+#pragma unroll
+            for (int k = N - 1; k >= 0; --k) {
+                const int dy = k / CWT - RY, dx = k % CWT - RX;
+                const int bp = i + dx + 4, bq = i - dx + 4;
+                const uint32_t pv = (R[RY + dy][bp >> 2] >> (8 * (bp & 3))) & 0xffu;
+                const uint32_t qv = (R[RY - dy][bq >> 2] >> (8 * (bq & 3))) & 0xffu;
+                // qv - pv wraps (bit 31 set) exactly when pv > qv; shift
+                // that bit in below the code's previous bits
+                code = __builtin_amdgcn_alignbit(code, qv - pv, 31);
+            }
+            const int xi = x + i;
+            if (xi < a.W)
+                out[(int64_t)y * a.out_pitch + xi] = yin && xi >= RX && xi < a.W - RX ? code : 0u;
+        }
+        return;
+    }
     const int lx = threadIdx.x & 63;
     for (int ty = threadIdx.x >> 6; ty < kCensusTH; ty += 4) {
         const int x = x0 + lx, y = y0 + ty;
