@@ -113,11 +113,18 @@ def main():
     ap.add_argument("--steps", type=int, default=125)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=16, help="frames per step")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="the step's frames are split over this many contexts, each on its "
+                         "own stream (throughput mode); the roofline and the stage times "
+                         "come from a separate one-stream run of the whole batch per call")
     ap.add_argument("--latency-runs", type=int, default=1000)
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--sweep-frames", type=int, default=256, metavar="N",
+                    help="frames per point of the frames-per-call x streams throughput "
+                         "sweep (0: no sweep)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (reference "
                          "for HBM byte counters)")
@@ -152,6 +159,48 @@ def main():
         sldf.quantize_lidar(lid_f.view(B * H, W), D, out=lid_q.view(B * H, W))
         ctx.run_batch(left, right, lid_q, disp, valid)
 
+    NS = args.streams
+    if NS < 1 or B % NS:
+        print("bench.py: --batch must be a multiple of --streams", file=sys.stderr)
+        sys.exit(2)
+
+    def multi_step(check_impl=0, sur=None):
+        # throughput mode: B / NS frames per call on each of NS streams; each
+        # stream reuses its own buffers in order, so no cross-stream waits
+        n = B // NS
+        strs = [stream] + [torch.cuda.Stream() for _ in range(NS - 1)]
+        cs, os_, lqs = [], [], []
+        for _ in range(NS):
+            c = sldf.Context(sldf.default_params(batch=n, check_impl=check_impl))
+            if sur is not None:
+                c.set_surrogate(*sur)
+            cs.append(c)
+            os_.append(c.new_outputs(n))
+            lqs.append(torch.empty((n, H, W), dtype=torch.int16, device="cuda"))
+
+        def run():
+            for i in range(NS):
+                sl = slice(i * n, (i + 1) * n)
+                sldf.quantize_lidar(lid_f[sl].reshape(n * H, W), D, out=lqs[i].view(n * H, W),
+                                    stream=strs[i])
+                cs[i].run_batch(left[sl], right[sl], lqs[i], os_[i][0], os_[i][1],
+                                stream=strs[i])
+
+        def outputs():
+            return (torch.cat([o[0] for o in os_]), torch.cat([o[1] for o in os_]))
+
+        return run, outputs
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0_ = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0_
+
     if args.copy_calibration > 0:
         # plain copy of known size: the reference reading for FETCH_SIZE /
         # WRITE_SIZE counters (read N bytes, write N bytes)
@@ -169,6 +218,14 @@ def main():
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
     K = args.steps
+    # headline: throughput mode over NS streams
+    run_m, outs_m = multi_step()
+    elapsed_m = timed(run_m, K)
+    fps_m = K * B / elapsed_m
+    print(f"[bench] {K} steps x {B} frames over {NS} streams in {elapsed_m * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+
+    # one stream, the whole batch per call: per-launch durations for the roofline
     ctx.timing_enable(K)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,6 +252,7 @@ def main():
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
                     unit="Tops/s", frac=round(achieved / peak, 4), traffic=traffic,
                     kernel="sgm_pair_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
+                    measured_in=f"one-stream run, {B} frames per call",
                     ops_per_launch=int(ops16 + ops32),
                     peak_basis="u16 recurrence at the packed-16 peak, the rest at the "
                                "32-bit peak",
@@ -208,8 +266,10 @@ def main():
     pipeline = dict(ops_per_frame=int(p16 + p32),
                     floor_fps_class_weighted=round(1 / floor_cw, 1),
                     floor_fps_int32=round(1 / floor_32, 1),
-                    frac_class_weighted=round(fps * floor_cw, 4),
-                    frac_int32=round(fps * floor_32, 4))
+                    frac_class_weighted=round(fps_m * floor_cw, 4),
+                    frac_int32=round(fps_m * floor_32, 4))
+    d_m, v_m = outs_m()
+    streams_identical = bool(torch.equal(d_m, disp) and torch.equal(v_m, valid))
     stage_ms = {k: round(v[0] / (K * B), 4) for k, v in stages.items()}
     stream = torch.cuda.current_stream()
 
@@ -261,12 +321,16 @@ def main():
         el = time.perf_counter() - t0
         st_l = ctx_l.timing_read()
         ctx_l.timing_enable(0)
+        run_lm, _ = multi_step(1, (sw, sb))
+        el_m = timed(run_lm, K)
         counts, limit = ctx_l.fallback_read(B)
         agree = float((valid_l == valid).float().mean().item())
         c1 = sldf.Context(sldf.default_params(batch=1, check_impl=1))
         c1.set_surrogate(sw, sb)
-        learned = dict(value=round(K * B / el, 2), unit="frames/s",
-                       speedup=round((K * B / el) / fps, 4), mask_agreement=round(agree, 6),
+        learned = dict(value=round(K * B / el_m, 2), unit="frames/s",
+                       speedup=round((K * B / el_m) / fps_m, 4),
+                       single_stream_frames_per_s=round(K * B / el, 2),
+                       mask_agreement=round(agree, 6),
                        fallback_frames=int(sum(c > limit for c in counts)), frames=B,
                        latency_ms=latency(c1),
                        stage_ms_per_frame={k: round(v[0] / (K * B), 4) for k, v in st_l.items()},
@@ -275,17 +339,63 @@ def main():
         print(f"[bench] learned {learned['value']} frames/s, agreement {agree:.5f}",
               file=sys.stderr, flush=True)
 
-    out = dict(metric=METRIC, value=round(fps, 2), unit="frames/s", n_gpus=1, steps=K,
-               warmup=args.warmup, ms_per_step=round(elapsed / K * 1e3, 4),
+    # throughput over frames per call x streams (one context per stream, the
+    # 16 generated frames repeated to fill larger calls), plain check
+    sweep = []
+    if args.sweep_frames > 0:
+        for kf in (1, 4, 8, 16, 32):
+            for ns in (1, 2):
+                idx = torch.arange(kf, device="cuda") % B
+                # gather on the padded buffers, so that rows keep the 16-byte pitch
+                pad = (B, H, left.stride(1))
+                lk = left.as_strided(pad, left.stride())[idx][:, :, :W]
+                rk = right.as_strided(pad, right.stride())[idx][:, :, :W]
+                fk = lid_f[idx].contiguous()
+                ctxs = [sldf.Context(sldf.default_params(batch=kf)) for _ in range(ns)]
+                outs = [c.new_outputs(kf) for c in ctxs]
+                lqs = [torch.empty((kf, H, W), dtype=torch.int16, device="cuda")
+                       for _ in range(ns)]
+                streams = [stream] + [torch.cuda.Stream() for _ in range(ns - 1)]
+
+                def round_():
+                    for i in range(ns):
+                        sldf.quantize_lidar(fk.view(kf * H, W), D, out=lqs[i].view(kf * H, W),
+                                            stream=streams[i])
+                        ctxs[i].run_batch(lk, rk, lqs[i], outs[i][0], outs[i][1],
+                                          stream=streams[i])
+
+                rounds = max(1, -(-args.sweep_frames // (kf * ns)))
+                for _ in range(2):
+                    round_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(rounds):
+                    round_()
+                torch.cuda.synchronize()
+                el_s = time.perf_counter() - t0
+                sweep.append(dict(frames_per_call=kf, streams=ns,
+                                  frames_per_s=round(rounds * kf * ns / el_s, 1)))
+                del ctxs, outs, lqs, lk, rk, fk
+        torch.cuda.empty_cache()
+        print(f"[bench] sweep {sweep}", file=sys.stderr, flush=True)
+
+    out = dict(metric=METRIC, value=round(fps_m, 2), unit="frames/s", n_gpus=1, steps=K,
+               warmup=args.warmup, ms_per_step=round(elapsed_m / K * 1e3, 4),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u16",
                data="synthetic",
                config=dict(workload="1242x375 D=128 census9x7 8-path SDSGM + DDC + "
                                     "stereo-LiDAR check (Tab. II), plain check",
                            frames_per_step=B, width=W, height=H, max_disp=D,
-                           check="plain", parallelism="single GPU, batched frames"),
+                           check="plain",
+                           parallelism=f"single GPU, {NS} streams x {B // NS} frames per call"),
+               single_stream=dict(frames_per_s=round(fps, 2), frames_per_call=B,
+                                  ms_per_step=round(elapsed / K * 1e3, 4),
+                                  outputs_identical_to_streams=streams_identical),
                latency_ms=lat_plain,
                stage_ms_per_frame=stage_ms, roofline=roofline, pipeline_floor=pipeline,
                learned_check=learned)
+    if sweep:
+        out["throughput_sweep"] = sweep
     if args.serving_seconds > 0:
         # serving: six rigs (640x480 D=64, 1242x375 D=128, 1920x1080 D=256),
         # Poisson arrivals at 300 frames/s in total, continuous batching
