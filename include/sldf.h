@@ -120,7 +120,14 @@ typedef struct {
                               directions of a pair as separate lines into two
                               cost terms, then one WTA pass (shortest critical
                               path, more S traffic; runs of more than one
-                              frame fall back to paired) */
+                              frame fall back to paired).  Single-frame
+                              contexts (batch 1) with 8 paths run the split
+                              schedule on two streams: the caller's and one
+                              the context creates (default priority),
+                              forked from and joined back into the caller's
+                              stream with events, so a call stays ordered
+                              on the caller's stream and can be captured
+                              into a graph */
 } sldf_params;
 
 /* Optional debug taps: device pointers, any may be NULL.  Written for frame

@@ -23,6 +23,10 @@ struct sldf_ctx {
     int n;            // census bits
     const uint16_t* sur_w;  // learned-check parameters (caller-owned)
     const float* sur_b;
+    // split schedule with 8 paths: a second stream for the pairs that run
+    // beside the main stream's passes, and the events that fork and join it
+    hipStream_t side;
+    hipEvent_t fork_ev, join_ev;
     // timing
     hipEvent_t* events;
     int32_t timing_cap;     // runs that fit in events
@@ -132,6 +136,13 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     const bool split = p->num_paths >= 4 && p->schedule != 1;
     void* s2l = split ? seg(Fs * cells * 2) : nullptr;
     void* s2r = split && needs_right(p) ? seg(Fs * cells * 2) : nullptr;
+    // 8 paths, single-frame contexts: a third term and checkpoints for the
+    // pairs of the second stream (batch contexts run single frames on one
+    // stream: a stream per context would share the few hardware queues with
+    // the caller's streams)
+    const bool split3 = split && p->num_paths == 8 && F <= (size_t)kSplitFrames;
+    void* s3l = split3 ? seg(Fs * cells * 2) : nullptr;
+    void* s3r = split3 && needs_right(p) ? seg(Fs * cells * 2) : nullptr;
     // checkpoints of the paired passes: the largest direction pair in use
     size_t ck_per_fv = 0;
     for (int k = 0; k < (p->num_paths >= 4 ? p->num_paths / 2 : 0); ++k) {
@@ -142,6 +153,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         ck_per_fv = n > ck_per_fv ? n : ck_per_fv;
     }
     void* ck = ck_per_fv ? seg(F * 2 * ck_per_fv) : nullptr;
+    void* ck2 = split3 ? seg(Fs * 2 * ck_per_fv) : nullptr;
     void* rb = seg(F * px * (size_t)(p->max_disp / 32) * 4);
     void* rho = seg(F * px * 2);
     void* feat = seg(F * px * 8);
@@ -167,7 +179,10 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->S_right = (uint16_t*)sr;
         b->S2[0] = (uint16_t*)s2l;
         b->S2[1] = (uint16_t*)s2r;
+        b->S3[0] = (uint16_t*)s3l;
+        b->S3[1] = (uint16_t*)s3r;
         b->ckpt = (uint32_t*)ck;
+        b->ckpt2 = (uint32_t*)ck2;
         b->rowbits = (uint32_t*)rb;
         b->rho = (uint16_t*)rho;
         b->feat = (uint32_t*)feat;
@@ -269,6 +284,21 @@ sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_byt
     plan(p, (char*)dev_workspace, &c->buf);
     c->need_right = needs_right(p);
     c->n = (p->census_w * p->census_h - 1) / 2;
+    if (c->buf.S3[0]) {
+        // default priority; non-blocking w.r.t. the null stream (the events
+        // order it against the caller's stream)
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return SLDF_EDEVICE;
+        }
+        if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+            if (c->fork_ev) hipEventDestroy(c->fork_ev);
+            hipStreamDestroy(c->side);
+            delete c;
+            return SLDF_EDEVICE;
+        }
+    }
     *out = c;
     return SLDF_OK;
 }
@@ -286,6 +316,12 @@ sldf_status sldf_destroy(sldf_ctx* ctx)
 {
     if (!ctx) return SLDF_OK;
     free_events(ctx);
+    if (ctx->side) {
+        hipStreamSynchronize(ctx->side);
+        hipEventDestroy(ctx->fork_ev);
+        hipEventDestroy(ctx->join_ev);
+        hipStreamDestroy(ctx->side);
+    }
     delete ctx;
     return SLDF_OK;
 }
@@ -495,6 +531,51 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         // takes S + S2 (4 paths).  The price is the S2 traffic.
         const bool split = p.schedule != 1 && n_frames <= kSplitFrames && b.S2[view_base] &&
                            (nv == 1 || b.S2[view_base + 1]);
+        if (split && npairs == 4 && ctx->side) {
+            // 8 paths on two streams: the main stream runs the split
+            // horizontal pair (r into S, -r into S2) and then the -x+y
+            // diagonal pair, which folds S2 into S; the second stream runs
+            // the vertical pair into S3 and then the +x+y diagonal pair on
+            // S3, with checkpoints of its own.  After the join one WTA pass
+            // takes S + S3.  Each line pass is as in the other schedules, so
+            // the results are identical; the two chains fill a machine that
+            // one single-frame pass leaves mostly idle.
+            ga.S2[0] = b.S2[0];
+            ga.S2[1] = b.S2[1];
+            SgmArgs gs = ga;
+            gs.S[0] = b.S3[0];
+            gs.S[1] = b.S3[1];
+            gs.ckpt = b.ckpt2;
+            if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
+                hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
+                return false;
+            for (int k = 1; k <= 2; ++k) {
+                gs.dx = kPairDirs[k][0];
+                gs.dy = kPairDirs[k][1];
+                gs.nlines = num_lines(W, H, gs.dx, gs.dy);
+                if (launch_sgm_pair(gs, D, k == 1 ? kFirst : kMiddle, nv, n_frames, ctx->side) !=
+                    hipSuccess)
+                    return false;
+                ctx->launches[stage] += 1;
+            }
+            if (hipEventRecord(ctx->join_ev, ctx->side) != hipSuccess) return false;
+            const int kd = D <= 128 ? 4 : 8;
+            ga.dx = kPairDirs[0][0];
+            ga.dy = kPairDirs[0][1];
+            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+            if (launch_sgm_dual(ga, D, kFirst, nv, n_frames, s, kd) != hipSuccess) return false;
+            ga.dx = kPairDirs[3][0];
+            ga.dy = kPairDirs[3][1];
+            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+            if (launch_sgm_pair(ga, D, kMiddle2, nv, n_frames, s) != hipSuccess) return false;
+            if (hipStreamWaitEvent(s, ctx->join_ev, 0) != hipSuccess) return false;
+            SgmArgs gw = ga;
+            gw.S2[0] = b.S3[0];
+            gw.S2[1] = b.S3[1];
+            if (launch_sgm_wta(gw, D, nv, n_frames, s) != hipSuccess) return false;
+            ctx->launches[stage] += 3;
+            return true;
+        }
         if (split) {
             ga.S2[0] = b.S2[0];
             ga.S2[1] = b.S2[1];

@@ -34,7 +34,10 @@ struct Buffers {
     uint16_t* S_right;    // [F][H][W][D] (only when the stereo check is on)
     uint16_t* S2[2];      // split schedule (single frames): second cost term per view,
                           // [min(F, kSplitFrames)][H][W][D]
+    uint16_t* S3[2];      // split schedule, 8 paths: the cost term of the pairs run on the
+                          // second stream, [min(F, kSplitFrames)][H][W][D]
     uint32_t* ckpt;       // paired-pass checkpoints, [F * views][lines][segs][D / 2] u32
+    uint32_t* ckpt2;      // checkpoints of the pairs on the second stream (split schedule)
     uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
     uint16_t* rho;        // [F][H][W] LiDAR residual
     uint32_t* feat;       // [F][H][W][2] surrogate cost features
