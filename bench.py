@@ -293,7 +293,46 @@ def main():
         return dict(p50=round(float(np.percentile(lats, 50)), 4),
                     p99=round(float(np.percentile(lats, 99)), 4), runs=int(lats.size))
 
+    def latency_graph(ctx1):
+        # the same calls captured once per frame into a HIP graph and
+        # replayed (no host launch work per kernel); every replay is checked
+        # against the frame's eager outputs, outside the timed window
+        d1, v1 = ctx1.new_outputs()
+        runs = args.latency_runs
+        if runs <= 0:
+            return None
+        ref = []
+        for j in range(B):
+            sldf.quantize_lidar(lid_f[j], D, out=lq1)
+            ctx1.run(left[j], right[j], lq1, d1, v1)
+            ref.append((d1.clone(), v1.clone()))
+        graphs = []
+        for j in range(B):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                sldf.quantize_lidar(lid_f[j], D, out=lq1)
+                ctx1.run(left[j], right[j], lq1, d1, v1)
+            graphs.append(g)
+        torch.cuda.synchronize()
+        lats, mism = [], 0
+        for i in range(runs + 5):
+            j = i % B
+            ev0.record(stream)
+            graphs[j].replay()
+            ev1.record(stream)
+            ev1.synchronize()
+            if i >= 5:
+                lats.append(ev0.elapsed_time(ev1))
+            mism += not (torch.equal(d1, ref[j][0]) and torch.equal(v1, ref[j][1]))
+        lats = np.array(lats)
+        del graphs
+        return dict(p50=round(float(np.percentile(lats, 50)), 4),
+                    p99=round(float(np.percentile(lats, 99)), 4), runs=int(lats.size),
+                    replays_identical_to_eager=mism == 0)
+
     lat_plain = latency(sldf.Context(sldf.default_params(batch=1)))
+    lat_plain_g = latency_graph(sldf.Context(sldf.default_params(batch=1)))
+    print(f"[bench] plain latency, graph replay {lat_plain_g}", file=sys.stderr, flush=True)
     print(f"[bench] plain latency {lat_plain}", file=sys.stderr, flush=True)
 
     # learned check: same frames, right-view pass skipped unless a frame falls back
@@ -333,6 +372,7 @@ def main():
                        mask_agreement=round(agree, 6),
                        fallback_frames=int(sum(c > limit for c in counts)), frames=B,
                        latency_ms=latency(c1),
+                       latency_graph_ms=latency_graph(c1),
                        stage_ms_per_frame={k: round(v[0] / (K * B), 4) for k, v in st_l.items()},
                        heldout_agreement=meta.get("eval", {}).get("no_fallback", {}).get(
                            "agreement"))
@@ -391,7 +431,7 @@ def main():
                single_stream=dict(frames_per_s=round(fps, 2), frames_per_call=B,
                                   ms_per_step=round(elapsed / K * 1e3, 4),
                                   outputs_identical_to_streams=streams_identical),
-               latency_ms=lat_plain,
+               latency_ms=lat_plain, latency_graph_ms=lat_plain_g,
                stage_ms_per_frame=stage_ms, roofline=roofline, pipeline_floor=pipeline,
                learned_check=learned)
     if sweep:
