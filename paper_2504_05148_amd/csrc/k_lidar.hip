@@ -52,6 +52,48 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+// rho_p = min |d - v| over the set bits v of the pixel's window mask m
+// (NW lanes per pixel, lane w holding word w; 65535 if empty), written by
+// the owner lane (w == 0) with the surrogate inputs when requested.
+template <int NW>
+__device__ __forceinline__ void emit_rho(const LidarArgs& a, uint32_t m, int d, int w, bool owner,
+                                         int64_t px, uint32_t s01, uint32_t cv)
+{
+    const int lo = 32 * w;
+    // this word's nearest set bits at index >= d and <= d
+    const uint32_t mu = d < lo ? m : (d - lo < 32 ? m & (0xffffffffu << (d - lo)) : 0u);
+    const uint32_t md =
+        d < lo ? 0u : (d - lo < 32 ? m & (0xffffffffu >> (31 - (d - lo))) : m);
+    const int up = mu ? lo + __builtin_ctz(mu) - d : 0xffff;
+    const int dn = md ? d - (lo + 31 - __builtin_clz(md)) : 0xffff;
+    int rho = up < dn ? up : dn;
+#pragma unroll
+    for (int q = 1; q < NW; q <<= 1) {
+        const int o = __shfl_xor(rho, q, NW);
+        rho = o < rho ? o : rho;
+    }
+    if (!owner) return;
+    a.rho[px] = (uint16_t)rho;
+    if (a.x0) {
+        // surrogate inputs: S(d*), second minimum, curvature, d*,
+        // residual, each an integer times a float32 scale, stored as
+        // bf16 (RNE)
+        const int r = rho < 32 ? rho : 32;
+        uint16_t f[5];
+        f[0] = f32_to_bf16_rne((float)(s01 & 0xffffu) * a.sS);
+        f[1] = f32_to_bf16_rne((float)(s01 >> 16) * a.sS);
+        f[2] = f32_to_bf16_rne((float)(int)cv * a.sS);
+        f[3] = f32_to_bf16_rne((float)d * a.sD);
+        f[4] = f32_to_bf16_rne((float)r * a.sR);
+        uint4 o;
+        o.x = f[0] | ((uint32_t)f[1] << 16);
+        o.y = f[2] | ((uint32_t)f[3] << 16);
+        o.z = f[4];
+        o.w = 0;
+        *reinterpret_cast<uint4*>(a.x0 + 8 * px) = o;
+    }
+}
+
 // Column pass: the window mask of pixel (x, y) is the OR of the row masks of
 // rows y - rc .. y + rc.  Sliding-window OR by the van Herk / Gil-Werman
 // scheme: with L = 2 rc + 1, a block takes a band of L output rows; the
@@ -93,7 +135,6 @@ __global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
         }
     }
     uint32_t g = 0u;
-    const int lo = 32 * w;
     const bool owner = xin && w == 0;
     const int64_t px0 = (int64_t)frame * a.px_stride + (int64_t)y0 * a.W + x;
     constexpr int kF = 8;
@@ -103,7 +144,9 @@ __global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
 #pragma unroll
         for (int k = 0; k < kF; ++k) {
             const int t = t0 + k;
-            const bool in = t < L && y0 + t < a.H && xin;
+            // (mask mode reads neither d* nor the features: they are being
+            // written by the path passes meanwhile)
+            const bool in = t < L && y0 + t < a.H && xin && !a.wmask;
             const int64_t px = px0 + (int64_t)t * a.W;
             v[k] = t > 0 && t < L ? row(t + L - 1) : 0u;
             dv[k] = in ? a.dstar[px] : 0;
@@ -116,42 +159,35 @@ __global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
             if (t >= L || y0 + t >= a.H) break;
             g |= v[k];
             const uint32_t m = hbuf[t * kColT + threadIdx.x] | g;
-            const int d = dv[k];
-            // this word's nearest set bits at index >= d and <= d
-            const uint32_t mu = d < lo ? m : (d - lo < 32 ? m & (0xffffffffu << (d - lo)) : 0u);
-            const uint32_t md =
-                d < lo ? 0u : (d - lo < 32 ? m & (0xffffffffu >> (31 - (d - lo))) : m);
-            const int up = mu ? lo + __builtin_ctz(mu) - d : 0xffff;
-            const int dn = md ? d - (lo + 31 - __builtin_clz(md)) : 0xffff;
-            int rho = up < dn ? up : dn;
-#pragma unroll
-            for (int q = 1; q < NW; q <<= 1) {
-                const int o = __shfl_xor(rho, q, NW);
-                rho = o < rho ? o : rho;
-            }
-            if (!owner) continue;
             const int64_t px = px0 + (int64_t)t * a.W;
-            a.rho[px] = (uint16_t)rho;
-            if (a.x0) {
-                // surrogate inputs: S(d*), second minimum, curvature, d*,
-                // residual, each an integer times a float32 scale, stored as
-                // bf16 (RNE)
-                const int r = rho < 32 ? rho : 32;
-                uint16_t f[5];
-                f[0] = f32_to_bf16_rne((float)(s01[k] & 0xffffu) * a.sS);
-                f[1] = f32_to_bf16_rne((float)(s01[k] >> 16) * a.sS);
-                f[2] = f32_to_bf16_rne((float)(int)cv[k] * a.sS);
-                f[3] = f32_to_bf16_rne((float)d * a.sD);
-                f[4] = f32_to_bf16_rne((float)r * a.sR);
-                uint4 o;
-                o.x = f[0] | ((uint32_t)f[1] << 16);
-                o.y = f[2] | ((uint32_t)f[3] << 16);
-                o.z = f[4];
-                o.w = 0;
-                *reinterpret_cast<uint4*>(a.x0 + 8 * px) = o;
+            if (a.wmask) {
+                // masks only (the residual follows once d* exists)
+                if (xin) a.wmask[px * NW + w] = m;
+                continue;
             }
+            emit_rho<NW>(a, m, dv[k], w, owner, px, s01[k], cv[k]);
         }
     }
+}
+
+// Residual and surrogate inputs from window masks computed before d*
+// existed (lidar_colbits_kernel with wmask): the same lane layout, one
+// pixel per NW lanes.
+template <int NW>
+__global__ __launch_bounds__(256) void lidar_rho_kernel(LidarArgs a)
+{
+    const int w = threadIdx.x % NW;
+    const int64_t q = (int64_t)blockIdx.x * (256 / NW) + threadIdx.x / NW;   // pixel of the batch
+    const int64_t npx = (int64_t)a.W * a.H;
+    const int frame = (int)(q / npx);
+    const bool in = frame < a.nframes;
+    const int64_t px = in ? (int64_t)frame * a.px_stride + (q - (int64_t)frame * npx) : 0;
+    const uint32_t m = in ? a.wmask[px * NW + w] : 0u;
+    const int d = in ? a.dstar[px] : 0;
+    const bool owner = in && w == 0;
+    const uint32_t s01 = owner && a.x0 ? a.feat[2 * px] : 0u;
+    const uint32_t cv = owner && a.x0 ? a.feat[2 * px + 1] : 0u;
+    emit_rho<NW>(a, m, d, w, owner, px, s01, cv);
 }
 
 hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s)
@@ -173,6 +209,20 @@ hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s)
     if (NW == 2) col(lidar_colbits_kernel<2>);
     else if (NW == 4) col(lidar_colbits_kernel<4>);
     else col(lidar_colbits_kernel<8>);
+    return hipGetLastError();
+}
+
+hipError_t launch_lidar_rho(const LidarArgs& a0, int nframes, hipStream_t s)
+{
+    if (!a0.wmask || !a0.dstar || !a0.rho || (a0.x0 && !a0.feat)) return hipErrorInvalidValue;
+    const int NW = a0.D / 32;
+    LidarArgs a = a0;
+    a.nframes = nframes;
+    const int64_t lanes = (int64_t)a.W * a.H * nframes * NW;
+    dim3 g((unsigned)((lanes + 255) / 256));
+    if (NW == 2) hipLaunchKernelGGL(lidar_rho_kernel<2>, g, dim3(256), 0, s, a);
+    else if (NW == 4) hipLaunchKernelGGL(lidar_rho_kernel<4>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(lidar_rho_kernel<8>, g, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -154,6 +154,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     }
     void* ck = ck_per_fv ? seg(F * 2 * ck_per_fv) : nullptr;
     void* ck2 = split3 ? seg(Fs * 2 * ck_per_fv) : nullptr;
+    void* wm = split3 ? seg(Fs * px * (size_t)(p->max_disp / 32) * 4) : nullptr;
     void* rb = seg(F * px * (size_t)(p->max_disp / 32) * 4);
     void* rho = seg(F * px * 2);
     void* feat = seg(F * px * 8);
@@ -183,6 +184,7 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->S3[1] = (uint16_t*)s3r;
         b->ckpt = (uint32_t*)ck;
         b->ckpt2 = (uint32_t*)ck2;
+        b->wmask = (uint32_t*)wm;
         b->rowbits = (uint32_t*)rb;
         b->rho = (uint16_t*)rho;
         b->feat = (uint32_t*)feat;
@@ -512,6 +514,28 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     // here, right view only in the gated fallback below
     const int nviews = ctx->need_right && !learned ? 2 : 1;
     ga.ckpt = b.ckpt;
+    // LiDAR window test arguments (used after the path passes, or for the
+    // masks on the second stream)
+    LidarArgs la;
+    la.lidar = lidar;
+    la.lidar_pitch = lidar_pitch;
+    la.lidar_fstride = lidar_frame_stride;
+    la.rowbits = b.rowbits;
+    la.dstar = b.dstar;
+    la.rho = b.rho;
+    la.feat = b.feat;
+    la.x0 = want_features ? b.x0 : nullptr;
+    la.px_stride = b.px_stride;
+    la.W = W;
+    la.H = H;
+    la.D = D;
+    la.rc = p.rc;
+    la.sS = 1.0f / (float)(p.num_paths * p.alpha_den * p.p2);
+    la.sD = 1.0f / (float)D;
+    la.sR = 1.0f / 32.0f;
+    la.wmask = nullptr;
+    la.nframes = n_frames;
+    bool masks_done = false;
     auto sgm_passes = [&](int view_base, int nv, int stage) {
         ga.view_base = view_base;
         if (p.num_paths == 1) {
@@ -549,6 +573,14 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
                 hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
                 return false;
+            if (view_base == 0 && b.wmask) {
+                // the LiDAR window masks first: the second stream's chain is
+                // the shorter one
+                LidarArgs lm = la;
+                lm.wmask = b.wmask;
+                if (launch_lidar_bits(lm, n_frames, ctx->side) != hipSuccess) return false;
+                masks_done = true;
+            }
             for (int k = 1; k <= 2; ++k) {
                 gs.dx = kPairDirs[k][0];
                 gs.dy = kPairDirs[k][1];
@@ -618,25 +650,15 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (mark(3) != hipSuccess) return SLDF_EDEVICE;
 
     // LiDAR window masks and residual (the LiDAR half of Eq. 6), surrogate
-    // inputs when requested
-    LidarArgs la;
-    la.lidar = lidar;
-    la.lidar_pitch = lidar_pitch;
-    la.lidar_fstride = lidar_frame_stride;
-    la.rowbits = b.rowbits;
-    la.dstar = b.dstar;
-    la.rho = b.rho;
-    la.feat = b.feat;
-    la.x0 = want_features ? b.x0 : nullptr;
-    la.px_stride = b.px_stride;
-    la.W = W;
-    la.H = H;
-    la.D = D;
-    la.rc = p.rc;
-    la.sS = 1.0f / (float)(p.num_paths * p.alpha_den * p.p2);
-    la.sD = 1.0f / (float)D;
-    la.sR = 1.0f / 32.0f;
-    if ((e = launch_lidar_bits(la, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
+    // inputs when requested; on two streams the masks (which do not need d*)
+    // were computed on the second stream beside the path passes
+    if (masks_done) {
+        LidarArgs lr = la;
+        lr.wmask = b.wmask;
+        if ((e = launch_lidar_rho(lr, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
+    } else if ((e = launch_lidar_bits(la, n_frames, s)) != hipSuccess) {
+        return SLDF_EDEVICE;
+    }
 
     // stereo-LiDAR consistency check (Sec. IV-C, Eq. 6)
     CheckArgs ka;

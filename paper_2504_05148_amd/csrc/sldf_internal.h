@@ -38,6 +38,8 @@ struct Buffers {
                           // second stream, [min(F, kSplitFrames)][H][W][D]
     uint32_t* ckpt;       // paired-pass checkpoints, [F * views][lines][segs][D / 2] u32
     uint32_t* ckpt2;      // checkpoints of the pairs on the second stream (split schedule)
+    uint32_t* wmask;      // LiDAR window masks computed on the second stream (split
+                          // schedule), [min(F, kSplitFrames)][H][W][D / 32]
     uint32_t* rowbits;    // [F][H][W][D / 32] LiDAR row-window masks
     uint16_t* rho;        // [F][H][W] LiDAR residual
     uint32_t* feat;       // [F][H][W][2] surrogate cost features
@@ -155,8 +157,10 @@ struct LidarArgs {
     uint16_t* rho;              // [F][H][W] LiDAR residual (65535 = none)
     const uint32_t* feat;       // [F][H][W][2] (S(d*) | S2nd << 16, curvature)
     uint16_t* x0;               // [F][H][W][8] bf16 surrogate inputs, or null
+    uint32_t* wmask;            // when set: the column pass stores the window masks
+                                // [F][H][W][D / 32] here instead of the residual
     int64_t px_stride;
-    int32_t W, H, D, rc;
+    int32_t W, H, D, rc, nframes;
     float sS, sD, sR;           // feature scales
 };
 
@@ -286,6 +290,8 @@ hipError_t launch_sgm_pair(const SgmArgs& a, int D, int mode, int nviews, int nf
 int64_t sgm_pair_ckpt_segs(int W, int H, int dx, int dy);
 hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s);
 hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s);
+// residual + surrogate inputs from a.wmask (masks of launch_lidar_bits with wmask)
+hipError_t launch_lidar_rho(const LidarArgs& a, int nframes, hipStream_t s);
 hipError_t launch_quantize(const float* in, int W, int H, int in_pitch, int D,
                            int16_t* out, int out_pitch, hipStream_t s);
 

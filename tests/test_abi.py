@@ -67,9 +67,9 @@ def test_workspace_size_plan():
     # for one frame, both views
     fixed = 2 * 2 * (W + 2 * D) * 4 + pw
     split = lambda F: min(F, 1) * 2 * cells * 2
-    # single-frame contexts with 8 paths: the second stream's cost term and
-    # checkpoints
-    split3 = lambda F: (2 * cells * 2 + ck) if F == 1 else 0
+    # single-frame contexts with 8 paths: the second stream's cost term,
+    # checkpoints and LiDAR window masks
+    split3 = lambda F: (2 * cells * 2 + ck + px * (D // 32) * 4) if F == 1 else 0
     exact = per_frame + fixed + split(1) + split3(1)
     assert exact <= n1 < exact + 20 * 256
     p.batch = 4
@@ -79,8 +79,8 @@ def test_workspace_size_plan():
     assert sldf.workspace_size(p) < n1 - cells
     # the paired schedule needs no second cost term
     p = sldf.default_params(schedule=1)
-    n_paired = n1 - split(1) - split3(1)
-    assert n_paired <= sldf.workspace_size(p) < n_paired + 20 * 256
+    n_paired = n1 - split(1) - split3(1)     # (each left-out segment also drops its padding)
+    assert n_paired - 20 * 256 <= sldf.workspace_size(p) < n_paired + 20 * 256
 
 
 @pytest.mark.parametrize("field,value,status", [
