@@ -136,6 +136,11 @@ __device__ __forceinline__ void run_line_split(const SgmArgs& a, const uint32_t*
 template <int G, int MODE, int NR>
 __global__ __launch_bounds__(256) void sgm_dir_kernel(SgmArgs a)
 {
+    // raised issue priority: on single frames this pass heads the longer of
+    // the two concurrent chains and shares its SIMDs with the other chain's
+    // pairs (measured: graph-replay p99 0.85 -> 0.82 ms; raising the pair
+    // after it too starves the other chain and is slower)
+    __builtin_amdgcn_s_setprio(3);
     constexpr int D = G * 2 * NR;
     __shared__ uint32_t pat[pattern_words(D)];
     build_pattern<D>(a, pat);
