@@ -184,13 +184,19 @@ sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes);
 /* Create a context on the current HIP device.  dev_workspace: caller-owned
    device buffer of at least sldf_workspace_size() bytes, 256-byte aligned,
    which must outlive the context.  *out receives a host-allocated handle.
+   Single-frame contexts (batch 1) with 8 paths and schedule 0 or 2 also
+   create a HIP stream (default priority, non-blocking) and two events for
+   the two-stream schedule; sldf_destroy releases them.
    Errors: as sldf_workspace_size, EALIGN (workspace), ENOMEM (ws_bytes too
-   small or host allocation failed), EDEVICE (no HIP device). */
+   small or host allocation failed), EDEVICE (no HIP device, or the stream or
+   events could not be created). */
 sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_bytes,
                         sldf_ctx** out);
 
-/* Release the handle (not the workspace).  NULL is accepted.  The caller
-   must have synchronised the stream of the last run first. */
+/* Release the handle (not the workspace) and the stream and events the
+   context created (after waiting for the work on that stream).  NULL is
+   accepted.  The caller must have synchronised the stream of the last run
+   first. */
 sldf_status sldf_destroy(sldf_ctx* ctx);
 
 /* Set the debug taps written by subsequent runs (copied; NULL clears). */
