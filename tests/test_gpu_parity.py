@@ -258,6 +258,25 @@ def test_paper_scale_batch_launch_configuration():
     for i in range(1, B - 1):
         g = run_gpu(frames[i], pkw, taps=False)
         assert (g["valid"] == valid[i]).all() and (g["disp"] == disp[i]).all()
+    # the benchmark's headline configuration: two contexts of 8 frames, each
+    # on its own stream, concurrently; the frames' outputs equal the 16-frame
+    # call bit for bit
+    print("case kitti 2 streams x 8 frames", flush=True)
+    n = B // 2
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    ctxs = [sldf.Context(sldf.default_params(batch=n)) for _ in range(2)]
+    outs = [c.new_outputs(n) for c in ctxs]
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for i, st in enumerate((main, side)):
+            sl = slice(i * n, (i + 1) * n)
+            ctxs[i].run_batch(left[sl], right[sl], lid[sl], outs[i][0], outs[i][1], stream=st)
+        torch.cuda.synchronize()
+        for i in range(2):
+            sl = slice(i * n, (i + 1) * n)
+            assert (outs[i][1].cpu().numpy() == valid[sl]).all(), (rep, i)
+            assert (outs[i][0].cpu().numpy() == disp[sl]).all(), (rep, i)
 
 
 def test_deterministic_repeat():
