@@ -134,6 +134,9 @@ def main():
               "(frames are independent, so more GPUs would each run their own "
               "frame stream with no exchange)", file=sys.stderr)
         sys.exit(2)
+    if args.streams < 1 or args.batch % args.streams:
+        print("bench.py: --batch must be a multiple of --streams", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_2504_05148_amd import sldf, synth
@@ -160,9 +163,6 @@ def main():
         ctx.run_batch(left, right, lid_q, disp, valid)
 
     NS = args.streams
-    if NS < 1 or B % NS:
-        print("bench.py: --batch must be a multiple of --streams", file=sys.stderr)
-        sys.exit(2)
 
     def multi_step(check_impl=0, sur=None):
         # throughput mode: B / NS frames per call on each of NS streams; each

@@ -1,0 +1,27 @@
+"""bench.py's command-line contract on the CPU: more than one GPU and a batch
+that the streams do not divide are refused with a message and exit code 2,
+before any GPU work."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_batch_must_split_over_streams():
+    r = _run("--batch", "16", "--streams", "3")
+    assert r.returncode == 2
+    assert "--streams" in r.stderr
+    assert r.stdout == ""
