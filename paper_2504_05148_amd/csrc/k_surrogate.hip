@@ -40,7 +40,8 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c)
 // 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out.
 // A block owns TW = 64 TPW output columns of one dilation lattice (the rows
 // r, r + d, r + 2d, ... of a residue r) and walks down up to kConvRowsMax of
-// its rows.  Output row i reads the input rows y - d, y, y + d, so
+// its rows (8 in single-frame calls).  Output row i reads the input rows
+// y - d, y, y + d, so
 // consecutive output rows share two of their three input rows: the input
 // rows (columns x0 - d .. x0 + TW - 1 + d, zero outside the image) pass
 // through a ring of kConvSlots LDS slots, each read from memory once per
@@ -246,7 +247,10 @@ static hipError_t launch_conv_tw(const ConvArgs& a, int nframes, hipStream_t s)
     if (d < 1 || d > kConvMaxDil || lds > (size_t)kConvMaxLds) return hipErrorInvalidValue;
     const int ntx = (a.W + 64 * TPW - 1) / (64 * TPW);
     const int lattice_rows = (a.H + d - 1) / d;                  // rows per residue, at most
-    const int qblocks = (lattice_rows + kConvRowsMax - 1) / kConvRowsMax;
+    // single frames: shorter walks, more blocks (one frame alone fills about
+    // one block per CU at 32 rows, and a block's rows run one after another)
+    const int rows_max = nframes == 1 ? 8 : kConvRowsMax;
+    const int qblocks = (lattice_rows + rows_max - 1) / rows_max;
     const int rows_blk = (lattice_rows + qblocks - 1) / qblocks;
     const int64_t nb = (int64_t)ntx * d * qblocks * nframes;
     dim3 grid((unsigned)((nb + 7) / 8 * 8));
