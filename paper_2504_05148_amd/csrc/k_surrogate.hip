@@ -37,20 +37,19 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c)
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out.
-// A block owns TW = 64 TPW output columns of one dilation lattice (the rows
-// r, r + d, r + 2d, ... of a residue r) and walks down up to kConvRowsMax of
-// its rows (8 in single-frame calls).  Output row i reads the input rows
-// y - d, y, y + d, so
-// consecutive output rows share two of their three input rows: the input
-// rows (columns x0 - d .. x0 + TW - 1 + d, zero outside the image) pass
+// 3x3 dilated convolution, NHWC bf16 in, bf16 (32 ch) or fp32 (1 ch) out. A
+// block owns TW = 64 TPW output columns of one dilation lattice (the rows r, r
+// + d, r + 2d, ... of a residue r) and walks down up to kConvRowsMax of its
+// rows (8 in single-frame calls).  Output row i reads the input rows y - d, y,
+// y + d, so consecutive output rows share two of their three input rows: the
+// input rows (columns x0 - d .. x0 + TW - 1 + d, zero outside the image) pass
 // through a ring of kConvSlots LDS slots, each read from memory once per
 // block, and are fetched kConvAhead rows ahead into registers so that their
 // latency overlaps the matrix work of the rows before.  Wave w computes the
 // 16-pixel tiles w, w + 4, .. of every output row; the weights (A operand)
-// stay in registers for the whole block.  Blocks go to the XCDs in
-// contiguous ranges, so neighbouring column tiles share the halo through one
-// L2.  Every output pixel sums its k-steps in order, whatever the tiling.
+// stay in registers for the whole block.  Blocks go to the XCDs in contiguous
+// ranges, so neighbouring column tiles share the halo through one L2.  Every
+// output pixel sums its k-steps in order, whatever the tiling.
 // ---------------------------------------------------------------------------
 constexpr int kConvMaxDil = 29;      // largest dilation (LDS budget of the ring)
 constexpr int kConvSlots = 4;        // three input rows in use, one being filled
