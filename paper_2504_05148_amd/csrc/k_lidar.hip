@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
     };
     // loads in chunks of kC rows, so that a chunk's loads are in flight
     // together instead of one dependent load per row
-    constexpr int kC = 16;
+    constexpr int kC = 48;
     uint32_t h = 0u;
     for (int base = L - 1; base >= 0; base -= kC) {
         uint32_t v[kC];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kColT) void lidar_colbits_kernel(LidarArgs a)
     uint32_t g = 0u;
     const bool owner = xin && w == 0;
     const int64_t px0 = (int64_t)frame * a.px_stride + (int64_t)y0 * a.W + x;
-    constexpr int kF = 8;
+    constexpr int kF = 16;
     for (int t0 = 0; t0 < L; t0 += kF) {
         uint32_t v[kF], s01[kF], cv[kF];
         int dv[kF];
