@@ -570,9 +570,15 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             gs.S[0] = b.S3[0];
             gs.S[1] = b.S3[1];
             gs.ckpt = b.ckpt2;
-            if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
-                hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
-                return false;
+            // the split pass heads the longer chain: it is enqueued first (the
+            // host's launch work for the other chain then overlaps it)
+            if (hipEventRecord(ctx->fork_ev, s) != hipSuccess) return false;
+            const int kd = D <= 128 ? 4 : 8;
+            ga.dx = kPairDirs[0][0];
+            ga.dy = kPairDirs[0][1];
+            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
+            if (launch_sgm_dual(ga, D, kFirst, nv, n_frames, s, kd) != hipSuccess) return false;
+            if (hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess) return false;
             if (view_base == 0 && b.wmask) {
                 // the LiDAR window masks first: the second stream's chain is
                 // the shorter one
@@ -591,11 +597,6 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
                 ctx->launches[stage] += 1;
             }
             if (hipEventRecord(ctx->join_ev, ctx->side) != hipSuccess) return false;
-            const int kd = D <= 128 ? 4 : 8;
-            ga.dx = kPairDirs[0][0];
-            ga.dy = kPairDirs[0][1];
-            ga.nlines = num_lines(W, H, ga.dx, ga.dy);
-            if (launch_sgm_dual(ga, D, kFirst, nv, n_frames, s, kd) != hipSuccess) return false;
             ga.dx = kPairDirs[3][0];
             ga.dy = kPairDirs[3][1];
             ga.nlines = num_lines(W, H, ga.dx, ga.dy);
