@@ -166,7 +166,10 @@ def test_paper_scale_dsgm():
 
 
 @pytest.mark.parametrize("W,H,D,paths", [(333, 77, 128, 8), (130, 19, 64, 8), (301, 40, 256, 8),
-                                         (300, 45, 256, 4), (97, 130, 64, 4)])
+                                         (300, 45, 256, 4), (97, 130, 64, 4),
+                                         # the smallest frame, and a disparity range wider
+                                         # than the image
+                                         (16, 16, 64, 8), (16, 16, 64, 4), (17, 16, 256, 8)])
 def test_ragged_shapes(W, H, D, paths):
     """Shapes that are not multiples of any tile, every disparity range."""
     spec = synth.robust_spec(W=W, H=H, D=D, density=0.05, lines=16)
