@@ -45,8 +45,10 @@ def _random_x0(F, H, W, seed):
 
 
 # sizes: ragged row blocks and column tiles of every dilation; H = 200 gives
-# seven row blocks per lattice at dilation 1
-@pytest.mark.parametrize("F,H,W", [(1, 37, 70), (2, 64, 129), (1, 200, 300)])
+# seven row blocks per lattice at dilation 1; 16 x 16 (the smallest frame) is
+# narrower than a tile and shorter than the largest dilation
+@pytest.mark.parametrize("F,H,W", [(1, 37, 70), (2, 64, 129), (1, 200, 300), (1, 16, 16),
+                                   (3, 16, 17)])
 def test_forward_matches_reference(F, H, W):
     """Activations within one bf16 rounding step, logits within a tolerance
     derived from fp32 accumulation of bf16 products."""
