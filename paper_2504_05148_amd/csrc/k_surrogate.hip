@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void bce_kernel(LossArgs a)
     sa[threadIdx.x] = i < a.px_stride ? agree : 0;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
+        if ((int)threadIdx.x < st) {
             sl[threadIdx.x] += sl[threadIdx.x + st];
             sc[threadIdx.x] += sc[threadIdx.x + st];
             sa[threadIdx.x] += sa[threadIdx.x + st];

@@ -295,8 +295,8 @@ sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_byt
         }
         if (hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
-            if (c->fork_ev) hipEventDestroy(c->fork_ev);
-            hipStreamDestroy(c->side);
+            if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+            (void)hipStreamDestroy(c->side);
             delete c;
             return SLDF_EDEVICE;
         }
@@ -308,7 +308,7 @@ sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_byt
 static void free_events(sldf_ctx* ctx)
 {
     if (!ctx->events) return;
-    for (int64_t i = 0; i < (int64_t)ctx->timing_cap * kMarks; ++i) hipEventDestroy(ctx->events[i]);
+    for (int64_t i = 0; i < (int64_t)ctx->timing_cap * kMarks; ++i) (void)hipEventDestroy(ctx->events[i]);
     delete[] ctx->events;
     ctx->events = nullptr;
     ctx->timing_cap = ctx->timing_runs = 0;
@@ -319,10 +319,11 @@ sldf_status sldf_destroy(sldf_ctx* ctx)
     if (!ctx) return SLDF_OK;
     free_events(ctx);
     if (ctx->side) {
-        hipStreamSynchronize(ctx->side);
-        hipEventDestroy(ctx->fork_ev);
-        hipEventDestroy(ctx->join_ev);
-        hipStreamDestroy(ctx->side);
+        // release paths: failures here leave nothing for the caller to do
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipEventDestroy(ctx->fork_ev);
+        (void)hipEventDestroy(ctx->join_ev);
+        (void)hipStreamDestroy(ctx->side);
     }
     delete ctx;
     return SLDF_OK;
@@ -339,7 +340,7 @@ sldf_status sldf_timing_enable(sldf_ctx* ctx, int32_t max_runs)
     if (!ctx->events) return SLDF_ENOMEM;
     for (int64_t i = 0; i < n; ++i) {
         if (hipEventCreate(&ctx->events[i]) != hipSuccess) {
-            for (int64_t j = 0; j < i; ++j) hipEventDestroy(ctx->events[j]);
+            for (int64_t j = 0; j < i; ++j) (void)hipEventDestroy(ctx->events[j]);
             delete[] ctx->events;
             ctx->events = nullptr;
             return SLDF_EDEVICE;
