@@ -92,19 +92,72 @@ def sgm_traffic(frames: int):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(n_frames: int):
+def _cpu_model():
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return None
+
+
+def _oracle_frames(kind, idxs):
     import oracle
     from paper_2504_05148_amd import synth
-    frames = [synth.kitti_frame(1000 + i) for i in range(n_frames)]
-    P = oracle.OracleParams()
-    lids = [oracle.quantize_lidar(f["lidar"], D) for f in frames]
+    if kind == "kitti":
+        frames = [synth.kitti_frame(i) for i in idxs]
+        P = oracle.OracleParams()
+    else:
+        frames = [synth.small_frame(i) for i in idxs]
+        P = oracle.OracleParams(W=320, H=96, D=64, cw=5, ch=5, num_paths=4)
+    return P, [(f["left"], f["right"], oracle.quantize_lidar(f["lidar"], P.D)) for f in frames]
+
+
+def _oracle_time(kind, idxs):
+    """Seconds the single-threaded C oracle takes for the frames (inputs
+    prepared beforehand, outside the timed region)."""
+    import oracle
+    P, inp = _oracle_frames(kind, idxs)
     t0 = time.perf_counter()
-    for f, lid in zip(frames, lids):
-        oracle.run(P, f["left"], f["right"], lid)
-    dt = time.perf_counter() - t0
-    return dict(value=n_frames / dt, unit="frames/s", cores=1, kind="oracle",
-                sample=f"{n_frames} synthetic 1242x375 D=128 frames, full method, "
-                       f"single-threaded C oracle ({dt:.1f} s)")
+    for left, right, lid in inp:
+        oracle.run(P, left, right, lid)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_frames: int, n_small: int, all_cores: bool):
+    """The CPU oracle on the host cores: n_frames paper-scale frames and
+    n_small small frames on one core; then one paper-scale frame on each of
+    N = usable cores concurrently (N processes), aggregate frames/s."""
+    dt = _oracle_time("kitti", range(1000, 1000 + n_frames))
+    out = dict(value=n_frames / dt, unit="frames/s", cores=1, kind="oracle",
+               sample=f"{n_frames} synthetic 1242x375 D=128 frames, full method (9x7 census, "
+                      f"8 paths, SDSGM, stereo-LiDAR check), single-threaded C oracle "
+                      f"({dt:.1f} s)",
+               cpu_model=_cpu_model())
+    if n_small > 0:
+        ds = _oracle_time("small", range(1000, 1000 + n_small))
+        out["small_frames"] = dict(value=round(n_small / ds, 3), unit="frames/s", cores=1,
+                                   sample=f"{n_small} synthetic 320x96 D=64 frames (5x5 "
+                                          f"census, 4 paths), {ds:.1f} s")
+    if all_cores:
+        from multiprocessing import get_context
+        try:
+            n = len(os.sched_getaffinity(0))
+        except AttributeError:
+            n = os.cpu_count() or 1
+        n = max(1, min(n, 16))
+        t0 = time.perf_counter()
+        with get_context("fork").Pool(n) as pool:
+            per = pool.starmap(_oracle_time, [("kitti", [2000 + i]) for i in range(n)])
+        wall = time.perf_counter() - t0
+        out["all_cores"] = dict(value=round(n / max(per), 3), unit="frames/s", cores=n,
+                                sample=f"{n} processes, one 1242x375 D=128 frame each, "
+                                       f"concurrently; slowest {max(per):.1f} s, "
+                                       f"wall incl. start-up {wall:.1f} s")
+    return out
 
 
 def main():
@@ -118,10 +171,14 @@ def main():
                          "own stream (throughput mode); the roofline and the stage times "
                          "come from a separate one-stream run of the whole batch per call")
     ap.add_argument("--latency-runs", type=int, default=1000)
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=5,
+                    help="paper-scale frames of the single-core oracle baseline")
+    ap.add_argument("--cpu-small-frames", type=int, default=50,
+                    help="320x96 D=64 frames of the single-core oracle baseline")
+    ap.add_argument("--no-cpu-all-cores", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--serving-seconds", type=float, default=3.0)
+    ap.add_argument("--serving-seconds", type=float, default=20.0)
     ap.add_argument("--sweep-frames", type=int, default=256, metavar="N",
                     help="frames per point of the frames-per-call x streams throughput "
                          "sweep (0: no sweep)")
@@ -456,7 +513,8 @@ def main():
                   flush=True)
         out["serving"] = srv
     if not args.no_cpu_baseline and args.cpu_frames > 0:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_frames)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_frames, args.cpu_small_frames,
+                                           not args.no_cpu_all_cores)
     print(json.dumps(out), flush=True)
 
 

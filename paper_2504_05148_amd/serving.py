@@ -18,6 +18,17 @@ admission is by HBM budget.  The scheduler
 
 and records latency = completion - arrival for every request.
 
+Failure handling, per rig (the other rigs are never affected):
+  - a rig whose parameters the library rejects (the backend's slot size
+    raises, e.g. an invalid shape or a 16-bit overflow bound) or whose one
+    slot is larger than the whole HBM budget is rejected at admission: its
+    requests fail at once instead of waiting for a slot that cannot exist;
+  - a failed launch fails its requests and returns its slot and stream;
+  - when the budget is full and a rig with waiting requests owns no slot, an
+    idle slot of another rig is released to make room;
+  - a rig that has sent nothing for `idle_timeout` seconds and has nothing
+    in flight gets its slots (its device state) released.
+
 The backend is an interface so the scheduler runs on the CPU in tests
 (`FakeBackend`); `SldfBackend` runs the library on the GPU.
 """
@@ -51,20 +62,27 @@ class FakeBackend:
     `slot_bytes[rig]` of budget.  Optional failure injection: launches of the
     rigs in `fail_rigs` raise."""
 
-    def __init__(self, cost, slot_bytes, fail_rigs=()):
+    def __init__(self, cost, slot_bytes, fail_rigs=(), bad_rigs=()):
         self.cost = cost
         self.slot_bytes_ = slot_bytes
         self.fail_rigs = set(fail_rigs)
+        self.bad_rigs = set(bad_rigs)       # parameters the library would reject
         self.clock = time.perf_counter
+        self.live = 0                       # slots made and not yet freed
+        self.freed = []
 
     def slot_bytes(self, rig):
+        if rig in self.bad_rigs:
+            raise ValueError(f"rig {rig}: invalid parameters")
         return self.slot_bytes_[rig]
 
     def make_slot(self, rig):
+        self.live += 1
         return dict(rig=rig)
 
     def free_slot(self, slot):
-        pass
+        self.live -= 1
+        self.freed.append(slot["rig"])
 
     def enqueue(self, slot, stream, reqs):
         if slot["rig"] in self.fail_rigs:
@@ -79,44 +97,88 @@ class FakeBackend:
 
 
 class Server:
-    def __init__(self, backend, n_rigs, hbm_budget, max_batch=4, n_streams=None):
+    def __init__(self, backend, n_rigs, hbm_budget, max_batch=4, n_streams=None,
+                 idle_timeout=None):
         self.be = backend
         self.n_rigs = n_rigs
         self.budget = hbm_budget
         self.max_batch = max_batch
+        self.idle_timeout = idle_timeout
         self.streams = list(range(n_streams or backend.n_streams()))
         self.slots = {r: [] for r in range(n_rigs)}      # all slots of a rig
         self.free = {r: [] for r in range(n_rigs)}       # idle slots
         self.used_bytes = 0
         self.peak_bytes = 0
         self.failed: list[Request] = []
+        self.rejected: dict[int, str] = {}               # rig -> reason
+        self._bytes: dict[int, int] = {}                 # rig -> bytes of one slot
+        self.released = collections.Counter()            # rig -> slots released
         self.batches = collections.Counter()
+
+    def _slot_bytes(self, rig):
+        """Bytes of one slot of the rig, or None when the rig is rejected
+        (parameters the library refuses, or a slot larger than the budget)."""
+        if rig in self.rejected:
+            return None
+        if rig not in self._bytes:
+            try:
+                b = int(self.be.slot_bytes(rig))
+            except Exception as e:      # invalid parameters: reject this rig only
+                self.rejected[rig] = f"parameters rejected: {e}"
+                return None
+            if b > self.budget:
+                self.rejected[rig] = (f"one slot ({b} B) exceeds the HBM budget "
+                                      f"({self.budget} B)")
+                return None
+            self._bytes[rig] = b
+        return self._bytes[rig]
+
+    def _new_slot(self, rig, b):
+        slot = self.be.make_slot(rig)
+        self.used_bytes += b
+        self.peak_bytes = max(self.peak_bytes, self.used_bytes)
+        self.slots[rig].append(slot)
+        return slot
+
+    def _release(self, rig, slot):
+        """Release an idle slot (its context and buffers) of a rig."""
+        self.free[rig].remove(slot)
+        self.slots[rig].remove(slot)
+        self.used_bytes -= self._bytes[rig]
+        self.be.free_slot(slot)
+        self.released[rig] += 1
 
     def preallocate(self, per_rig):
         """Create up to per_rig idle slots per rig (round-robin, within the
         budget) so that no allocation happens while serving."""
         for _ in range(per_rig):
             for rig in range(self.n_rigs):
-                b = self.be.slot_bytes(rig)
-                if self.used_bytes + b > self.budget:
+                b = self._slot_bytes(rig)
+                if b is None or self.used_bytes + b > self.budget:
                     continue
-                slot = self.be.make_slot(rig)
-                self.used_bytes += b
-                self.peak_bytes = max(self.peak_bytes, self.used_bytes)
-                self.slots[rig].append(slot)
-                self.free[rig].append(slot)
+                self.free[rig].append(self._new_slot(rig, b))
 
     def _get_slot(self, rig):
+        """An idle slot of the rig, a new one within the budget (releasing
+        idle slots of other rigs when the budget is full and the rig owns
+        none), or None (wait for one of its slots, or the rig is rejected)."""
         if self.free[rig]:
             return self.free[rig].pop()
-        b = self.be.slot_bytes(rig)
+        b = self._slot_bytes(rig)
+        if b is None:
+            return None
+        if self.used_bytes + b > self.budget and not self.slots[rig]:
+            # the rig owns no slot at all: take room from idle slots of the
+            # rigs holding the most of them
+            while self.used_bytes + b > self.budget:
+                donors = [r for r in range(self.n_rigs) if r != rig and self.free[r]]
+                if not donors:
+                    break
+                d = max(donors, key=lambda r: len(self.free[r]))
+                self._release(d, self.free[d][0])
         if self.used_bytes + b > self.budget:
             return None
-        slot = self.be.make_slot(rig)
-        self.used_bytes += b
-        self.peak_bytes = max(self.peak_bytes, self.used_bytes)
-        self.slots[rig].append(slot)
-        return slot
+        return self._new_slot(rig, b)
 
     def run(self, arrivals, realtime=True, progress=None):
         """arrivals: list of (t, rig, frame) sorted by t.  Returns the list of
@@ -130,6 +192,7 @@ class Server:
         clock = self.be.clock
         t0 = clock()
         last_report = t0
+        last_seen = {r: 0.0 for r in range(self.n_rigs)}     # last arrival per rig
         while pending or in_flight or any(queues.values()):
             now = clock() - t0
             if not realtime and not in_flight and not any(queues.values()) and pending:
@@ -137,7 +200,19 @@ class Server:
                 now = clock() - t0
             while pending and pending[0].arrival <= now:
                 r = pending.popleft()
-                queues[r.rig].append(r)
+                last_seen[r.rig] = r.arrival
+                if self._slot_bytes(r.rig) is None:
+                    self.failed.append(r)         # rejected rig: fail at admission
+                else:
+                    queues[r.rig].append(r)
+            # rigs silent for longer than the timeout release their idle slots
+            if self.idle_timeout is not None:
+                for rig in range(self.n_rigs):
+                    if (self.free[rig] and not queues[rig]
+                            and len(self.free[rig]) == len(self.slots[rig])
+                            and now - last_seen[rig] > self.idle_timeout):
+                        for slot in list(self.free[rig]):
+                            self._release(rig, slot)
             # retire finished launches
             still = []
             for h, slot, st, batch in in_flight:
@@ -350,8 +425,9 @@ def make_pools(n_rigs, pool_size, workers=14):
 
 def run_serving(duration=5.0, pool_size=16, max_batch=4, hbm_budget=96 << 30,
                 check_impl=0, surrogate=None, pools=None, rates=None, keep_outputs=False,
-                n_streams=8, log=None, prealloc=3):
-    """Run the six-rig mix on the GPU; returns (summary dict, backend, finished)."""
+                n_streams=8, log=None, prealloc=3, idle_timeout=1.0):
+    """Run the six-rig mix on the GPU; returns (summary dict, backend, finished).
+    Rigs that send nothing for idle_timeout seconds release their slots."""
     import torch
     from paper_2504_05148_amd import synth
     n_rigs = len(synth.SERVING_RIGS)
@@ -361,7 +437,7 @@ def run_serving(duration=5.0, pool_size=16, max_batch=4, hbm_budget=96 << 30,
     rates = rates or [50.0] * n_rigs
     be = SldfBackend(rigs, pools, max_batch, check_impl, surrogate, n_streams=n_streams,
                      keep_outputs=keep_outputs)
-    srv = Server(be, n_rigs, hbm_budget, max_batch)
+    srv = Server(be, n_rigs, hbm_budget, max_batch, idle_timeout=idle_timeout)
     srv.preallocate(prealloc)
     # warm-up: one launch per rig
     warm = [(0.0, rig, 0) for rig in range(n_rigs)]
@@ -377,7 +453,8 @@ def run_serving(duration=5.0, pool_size=16, max_batch=4, hbm_budget=96 << 30,
     summ.update(batches=dict(sorted(srv.batches.items())), peak_slot_bytes=srv.peak_bytes,
                 budget_bytes=hbm_budget, slots={r: len(s) for r, s in srv.slots.items()},
                 offered_frames_per_s=round(len(arr) / duration, 2), duration_s=duration,
-                check="learned" if check_impl else "plain")
+                check="learned" if check_impl else "plain", rejected=dict(srv.rejected),
+                released=dict(srv.released))
     return summ, be, fin
 
 

@@ -298,3 +298,43 @@ def test_run_rejects_misaligned_pitch():
     with pytest.raises(sldf.SldfError) as ei:
         ctx.run(img, img, lid)
     assert ei.value.status == sldf.EALIGN
+
+
+# The other workload shapes at full size, one frame each, every tap compared:
+# the 640 x 480 robustness frames at D = 64 and 128, the indoor variant
+# (640 x 480, D = 256, disparities 40-250, 1 % uniform LiDAR sample) and the
+# 1920 x 1080, D = 256 serving frame (long lines, 256-wide disparity vectors).
+WORKLOADS = {
+    "640x480_D64": lambda: synth.make_frame(synth.robust_spec(W=640, H=480, D=64, density=0.05),
+                                            synth.CONFIG_IDS["robust"], 640064),
+    "640x480_D128": lambda: synth.make_frame(synth.robust_spec(W=640, H=480, D=128,
+                                                               density=0.02, lines=32),
+                                             synth.CONFIG_IDS["robust"], 640128),
+    "indoor_640x480_D256": lambda: synth.make_frame(synth.INDOOR, synth.CONFIG_IDS["robust"],
+                                                    640256),
+    "1920x1080_D256": lambda: synth.make_frame(synth.serving_spec(4),
+                                               synth.CONFIG_IDS["serving"], 4),
+}
+
+
+_WORKLOAD_ORACLE = {}
+
+
+def _workload_case(name):
+    # one oracle run per workload, shared by both schedules' tests (the
+    # 1920 x 1080 x 256 oracle takes about a minute on one core)
+    if name not in _WORKLOAD_ORACLE:
+        f = WORKLOADS[name]()
+        H, W = f["left"].shape
+        pkw = _params(W, H, int(f["D"]))
+        _WORKLOAD_ORACLE.clear()
+        _WORKLOAD_ORACLE[name] = (f, pkw, run_oracle(f, pkw))
+    return _WORKLOAD_ORACLE[name]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_workload_shapes(name, schedule):
+    f, pkw, o = _workload_case(name)
+    print(f"case workload {name} schedule={schedule}", flush=True)
+    assert_parity(run_gpu(f, dict(pkw, schedule=schedule)), o, pkw)
