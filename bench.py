@@ -68,16 +68,17 @@ def pipeline_ops_per_frame():
 
 
 HBM_PEAK = 8.0e12
-# sources of the SGM pair kernel: a counter summary taken on other sources
-# no longer describes it
-SGM_SOURCES = ("k_sgm_pair.hip", "sgm_common.h", "sldf_internal.h")
+# sources of the SGM path kernel (the two-sweep kernel for runs of 16 or more
+# frames): a counter summary taken on other sources no longer describes it
+SGM_SOURCES = ("k_sgm_sweep.hip", "sgm_common.h", "sldf_internal.h")
+SWEEP_MIN_FRAMES = 16
 
 
 def sgm_traffic(frames: int):
     """HBM bytes per SGM launch from the committed counter summary, if it
     was taken on the current kernel source and the same launch size."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sgm_pair_kernel_traffic.json")
+    path = os.path.join(ROOT, "profiles", "sgm_sweep_kernel_traffic.json")
     csrc = os.path.join(ROOT, "paper_2504_05148_amd", "csrc")
     try:
         rec = json.load(open(path))
@@ -165,7 +166,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=125)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=16, help="frames per step")
+    ap.add_argument("--batch", type=int, default=64, help="frames per step")
     ap.add_argument("--streams", type=int, default=2,
                     help="the step's frames are split over this many contexts, each on its "
                          "own stream (throughput mode); the roofline and the stage times "
@@ -308,7 +309,8 @@ def main():
     traffic = sgm_traffic(B)
     roofline = dict(bound="alu", achieved=round(achieved / 1e12, 3), peak=round(peak / 1e12, 3),
                     unit="Tops/s", frac=round(achieved / peak, 4), traffic=traffic,
-                    kernel="sgm_pair_kernel", avg_launch_us=round(avg_launch_s * 1e6, 2),
+                    kernel="sgm_sweep_kernel" if B >= SWEEP_MIN_FRAMES else "sgm_pair_kernel",
+                    avg_launch_us=round(avg_launch_s * 1e6, 2),
                     measured_in=f"one-stream run, {B} frames per call",
                     ops_per_launch=int(ops16 + ops32),
                     peak_basis="u16 recurrence at the packed-16 peak, the rest at the "
@@ -440,7 +442,7 @@ def main():
     # 16 generated frames repeated to fill larger calls), plain check
     sweep = []
     if args.sweep_frames > 0:
-        for kf in (1, 4, 8, 16, 32):
+        for kf in (1, 4, 8, 16, 32, 64):
             for ns in (1, 2):
                 idx = torch.arange(kf, device="cuda") % B
                 # gather on the padded buffers, so that rows keep the 16-byte pitch

@@ -113,15 +113,22 @@ typedef struct {
                               t = |d - prior| */
     int32_t huber_k;       /* Huber threshold k >= 1 (prior_cost 2) */
     int32_t schedule;      /* order of the path passes (results identical):
-                              0 = automatic (split for single-frame runs,
-                              paired otherwise); 1 = paired: both
-                              directions of a pair on one line, S read and
-                              written once per pair; 2 = split: the two
-                              directions of a pair as separate lines into two
-                              cost terms, then one WTA pass (shortest critical
-                              path, more S traffic; runs of more than one
-                              frame fall back to paired).  Single-frame
-                              contexts (batch 1) with 8 paths run the split
+                              0 = automatic (two sweeps for runs of 16 or
+                              more frames, split for single frames, paired
+                              otherwise);
+                              1 = paired: both directions of a pair on one
+                              line, S read and written once per pair;
+                              2 = split: the two directions of a pair as
+                              separate lines into two cost terms, then one WTA
+                              pass (shortest critical path, more S traffic;
+                              runs of more than one frame fall back to paired);
+                              3 = two sweeps: rows walk the image top to
+                              bottom with four directions (S written once),
+                              then bottom to top with the other four and the
+                              WTA (S read once); rows are handed from one
+                              band of rows to the next through a workspace
+                              buffer.  Single-frame contexts (batch 1) with
+                              8 paths and schedule 0 or 2 run the split
                               schedule on two streams: the caller's and one
                               the context creates (default priority),
                               forked from and joined back into the caller's
@@ -147,7 +154,11 @@ typedef struct {
                                          |d - d*| >= 2, curvature
                                          S(d*-1) - 2 S(d*) + S(d*+1), each times
                                          1 / (num_paths P2'); d* / D;
-                                         min(rho, 32) / 32; three zeros */
+                                         min(rho, 32) / 32; three zeros
+     sweep_errors        int32  [1]      two-sweep schedule: nonzero if a wait
+                                         for the row band above timed out (the
+                                         results are then not valid); written
+                                         by every run of that schedule */
 typedef struct {
     uint32_t* census_l;
     uint32_t* census_r;
@@ -158,6 +169,7 @@ typedef struct {
     float* dsub;
     uint16_t* rho;
     uint16_t* features;
+    int32_t* sweep_errors;
 } sldf_taps;
 
 typedef struct sldf_ctx sldf_ctx;

@@ -587,6 +587,7 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int v)
 
 hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s)
 {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }

@@ -21,6 +21,7 @@ struct sldf_ctx {
     sldf_taps taps;
     int need_right;   // right-view pass needed (stereo half of the check)
     int n;            // census bits
+    int sweep_ready;  // handoff buffer and sync words of the two-sweep schedule zeroed
     const uint16_t* sur_w;  // learned-check parameters (caller-owned)
     const float* sur_b;
     // split schedule with 8 paths: a second stream for the pairs that run
@@ -75,7 +76,7 @@ sldf_status validate(const sldf_params* p)
          !(p->uncertain_margin >= 0.f)))
         return SLDF_EINVAL;
     if (p->subpixel != 0 && p->subpixel != 1) return SLDF_EINVAL;
-    if (p->schedule < 0 || p->schedule > 2) return SLDF_EINVAL;
+    if (p->schedule < 0 || p->schedule > 3) return SLDF_EINVAL;
     if (p->prior_cost < 0 || p->prior_cost > 2 || p->huber_k < 1 || p->huber_k > 4096)
         return SLDF_EINVAL;
     if (p->batch < 1 || p->batch > 4096) return SLDF_EINVAL;
@@ -164,6 +165,13 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
     void* act1 = learned ? seg(F * px * 64) : nullptr;
     void* logits = learned ? seg(F * px * 4) : nullptr;
     void* counter = learned ? seg(F * 4) : nullptr;
+    // two-sweep schedule (runs of kSweepMinFrames or more frames, or schedule 3)
+    const bool sweep = p->num_paths >= 4 &&
+                       (p->schedule == 3 || (p->schedule == 0 && F >= (size_t)kSweepMinFrames));
+    void* hand = sweep ? seg(F * 2 * (size_t)sweep_hand_bytes_per_fv(p->width, p->height,
+                                                                      p->max_disp))
+                       : nullptr;
+    void* sync = sweep ? seg(16) : nullptr;
     if (b) {
         b->census_l = base ? (uint32_t*)cl + cpitch + p->max_disp : nullptr;
         b->census_r = base ? (uint32_t*)cr + cpitch + p->max_disp : nullptr;
@@ -193,6 +201,11 @@ size_t plan(const sldf_params* p, char* base, Buffers* b)
         b->act[1] = (uint16_t*)act1;
         b->logits = (float*)logits;
         b->counter = (int32_t*)counter;
+        b->hand = (uint32_t*)hand;
+        b->sync = (int32_t*)sync;
+        b->hand_bytes = sweep ? F * 2 * (size_t)sweep_hand_bytes_per_fv(p->width, p->height,
+                                                                         p->max_disp)
+                              : 0;
         b->px_stride = (int64_t)px;
         b->S_stride = (int64_t)cells;
     }
@@ -547,6 +560,25 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             ctx->launches[stage] += 1;
             return true;
         }
+        if (b.hand && (p.schedule == 3 || (p.schedule == 0 && n_frames >= kSweepMinFrames))) {
+            // two sweeps: S written once (sweep A, four directions) and read
+            // once (sweep B, the other four, WTA); the handoff buffer and the
+            // launch words start at zero (then every launch leaves them so)
+            if (!ctx->sweep_ready) {
+                if (launch_fill_i32((int32_t*)b.hand, (int)(b.hand_bytes / 4), 0, s) != hipSuccess ||
+                    launch_fill_i32(b.sync, 4, 0, s) != hipSuccess)
+                    return false;
+                ctx->sweep_ready = 1;
+            }
+            ga.hand = b.hand;
+            ga.sync = b.sync;
+            ga.npaths = p.num_paths;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (launch_sgm_sweep(ga, D, pass, nv, n_frames, s) != hipSuccess) return false;
+                ctx->launches[stage] += 1;
+            }
+            return true;
+        }
         const int npairs = p.num_paths / 2;
         // single frames: the split schedule.  The horizontal pair (the
         // longest lines, and the fewest) runs its two directions as separate
@@ -760,6 +792,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         return SLDF_EDEVICE;
     if (cp(t.rho, b.rho, px * 2) != hipSuccess || cp(t.features, b.x0, px * 16) != hipSuccess)
         return SLDF_EDEVICE;
+    if (b.sync && cp(t.sweep_errors, b.sync + 2, 4) != hipSuccess) return SLDF_EDEVICE;
     return SLDF_OK;
 }
 

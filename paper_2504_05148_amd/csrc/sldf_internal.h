@@ -47,6 +47,9 @@ struct Buffers {
     uint16_t* act[2];     // [F][H][W][32] bf16 CNN activations (learned check)
     float* logits;        // [F][H][W] (learned check)
     int32_t* counter;     // [F] uncertain pixels per frame (learned check)
+    uint32_t* hand;       // two-sweep schedule: row-band handoff, [F * 2][bands - 1][W][chunks]
+    int32_t* sync;        // two-sweep schedule: ticket, done, error words
+    size_t hand_bytes;
     int64_t px_stride;    // W * H
     int64_t S_stride;     // W * H * D
 };
@@ -142,6 +145,12 @@ struct SgmArgs {
     const int32_t* gate;
     int32_t gate_limit;
     int32_t view_base;          // first view of the launch (1 = right view only)
+    // two-sweep schedule: per-pixel handoff between row bands (zero between
+    // launches) and the ticket / done / error words of the launch
+    uint32_t* hand;
+    int32_t* sync;
+    int32_t npaths;
+    int32_t rows_per_band;      // filled by launch_sgm_sweep
     // launch geometry (filled by launch_sgm_dir)
     int32_t blocks_per_fv;      // blocks per (frame, view)
     int32_t nviews;
@@ -284,6 +293,19 @@ hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nf
 hipError_t launch_sgm_wta(const SgmArgs& a, int D, int nviews, int nframes, hipStream_t s);
 // runs of at most this many frames use the split schedule
 constexpr int kSplitFrames = 1;
+
+// Two-sweep schedule (k_sgm_sweep.hip): sweep A (pass 0) stores the first
+// four directions' share of S, sweep B (pass 1) adds the other four and
+// takes the WTA.  a.npaths is 4 or 8; a.hand / a.sync as in SgmArgs.
+hipError_t launch_sgm_sweep(const SgmArgs& a, int D, int pass, int nviews, int nframes,
+                            hipStream_t s);
+int sweep_rows_host(int D);
+int sweep_bands(int H, int D);
+int64_t sweep_hand_bytes_per_fv(int W, int H, int D);
+// runs of at least this many frames take the two-sweep schedule by default
+// (smaller runs leave the machine idle along the sweeps' row skew and are
+// faster with the paired passes)
+constexpr int kSweepMinFrames = 16;
 // two opposite directions (dx, dy) and (-dx, -dy) in one launch
 hipError_t launch_sgm_pair(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                            hipStream_t s);

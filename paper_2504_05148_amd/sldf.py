@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
 class Taps(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in
                 ("census_l", "census_r", "prior", "cost_sum", "dstar", "dright", "dsub",
-                 "rho", "features")]
+                 "rho", "features", "sweep_errors")]
 
 
 class SldfError(RuntimeError):

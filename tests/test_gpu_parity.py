@@ -111,8 +111,10 @@ SMALL = dict(census_w=5, census_h=5, num_paths=4)
 
 
 # path pass schedules (identical results): 1 = paired directions on one
-# line, 2 = split (each direction its own line pass, then one WTA pass)
-SCHEDULES = [1, 2]
+# line, 2 = split (each direction its own line pass, then one WTA pass),
+# 3 = two sweeps (four directions per walk over the rows, bands of rows
+# handed on through the workspace)
+SCHEDULES = [1, 2, 3]
 
 
 @pytest.mark.parametrize("idx", [0, 1])
