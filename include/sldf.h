@@ -229,6 +229,26 @@ sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
                      float* disp_out, uint8_t* valid_out, int32_t out_pitch,
                      void* hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+   serving loops, harnesses that forbid allocation): sldf_run without a
+   context or a caller workspace.  The workspace is a static device array of
+   SLDF_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the process
+   ends and shared by every call on that GPU: calls that overlap on one GPU
+   (several streams or threads) race and must be serialised by the caller.
+   One frame, plain check only (params->check_impl 0; batch is taken as 1),
+   run on the caller's stream with the paired schedule (schedule 0 and 2 run
+   as 1, 3 stays; results are the same for every schedule).  Pointers and
+   layouts as for sldf_run.  No hipMalloc / hipFree or other allocation.
+   Errors: as sldf_workspace_size and sldf_run; EINVAL (check_impl != 0);
+   ENOMEM when the frame's workspace (sldf_workspace_size with batch 1 and
+   that schedule) exceeds SLDF_NOALLOC_SCRATCH_BYTES: 320 x 96 and 640 x 480
+   at D = 64 fit, 1242 x 375 at D = 128 does not. */
+#define SLDF_NOALLOC_SCRATCH_BYTES (128u << 20)
+sldf_status sldf_run_noalloc(const sldf_params* params, const uint8_t* left,
+                             const uint8_t* right, int32_t img_pitch, const int16_t* lidar,
+                             int32_t lidar_pitch, float* disp_out, uint8_t* valid_out,
+                             int32_t out_pitch, void* hip_stream);
+
 /* Process n_frames (1 <= n_frames <= p.batch) frames of the context's shape
    in one pass; frame i of each array starts at base + i * (its frame stride,
    in elements; image strides must keep 16-byte alignment).  Same layouts and

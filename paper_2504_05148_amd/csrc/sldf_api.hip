@@ -1,6 +1,7 @@
 // C ABI of libsldf.so: parameter validation, workspace plan and the launch
 // sequence of one frame batch (Fig. 1 flow of the paper).
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <string.h>
 
@@ -803,6 +804,70 @@ sldf_status sldf_run(sldf_ctx* ctx, const uint8_t* left, const uint8_t* right,
 {
     return sldf_run_batch(ctx, 1, left, right, img_pitch, 0, lidar, lidar_pitch, 0,
                           disp_out, valid_out, out_pitch, 0, hip_stream);
+}
+
+}  // extern "C"
+
+// Workspace of sldf_run_noalloc: one static device array per GPU, fixed size.
+// In host code `scratch` names a host-side stand-in, not a device address:
+// its device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is handed to the kernels.
+static __device__ __align__(256) unsigned char scratch[SLDF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices] = {};
+
+// device address of this device's scratch array (dev is current), or null
+void* scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+sldf_status sldf_run_noalloc(const sldf_params* params, const uint8_t* left,
+                             const uint8_t* right, int32_t img_pitch, const int16_t* lidar,
+                             int32_t lidar_pitch, float* disp_out, uint8_t* valid_out,
+                             int32_t out_pitch, void* hip_stream)
+{
+    if (!params) return SLDF_EINVAL;
+    sldf_params p = *params;
+    sldf_status st = validate(&p);
+    if (st != SLDF_OK) return st;
+    if (p.check_impl != 0) return SLDF_EINVAL;     // no surrogate weights here
+    // one frame on the caller's stream only: the paired schedule (no second
+    // stream, no split cost terms; the results are the same for every schedule)
+    p.batch = 1;
+    if (p.schedule != 3) p.schedule = 1;
+    const size_t need = plan(&p, nullptr, nullptr);
+    if (need > (size_t)SLDF_NOALLOC_SCRATCH_BYTES) return SLDF_ENOMEM;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SLDF_EDEVICE;
+    char* ws = (char*)scratch_ptr(dev);
+    if (!ws) return SLDF_EDEVICE;
+    // a context on the stack over the static workspace: no host or device
+    // allocation; everything the passes read is written earlier in the call
+    sldf_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.p = p;
+    c.device = dev;
+    plan(&p, ws, &c.buf);
+    c.need_right = needs_right(&p);
+    c.n = (p.census_w * p.census_h - 1) / 2;
+    return sldf_run_batch(&c, 1, left, right, img_pitch, 0, lidar, lidar_pitch, 0, disp_out,
+                          valid_out, out_pitch, 0, hip_stream);
 }
 
 int32_t sldf_surrogate_num_weights(void) { return kSurNW; }

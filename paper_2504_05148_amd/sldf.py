@@ -74,6 +74,8 @@ def lib():
         L.sldf_run_batch.argtypes = [_vp, _i32, _vp, _vp, _i32, _i64, _vp, _i32, _i64,
                                      _vp, _vp, _i32, _i64, _vp]
         L.sldf_lidar_quantize.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]
+        L.sldf_run_noalloc.argtypes = [ctypes.POINTER(Params), _vp, _vp, _i32, _vp, _i32, _vp,
+                                       _vp, _i32, _vp]
         L.sldf_timing_enable.argtypes = [_vp, _i32]
         L.sldf_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -91,7 +93,7 @@ def lib():
                                                 _vp, _vp, _vp, _vp, _f, _f, _f, _f, _i32,
                                                 _i32, _vp, _sz, _vp, _vp, _vp]
         for f in ("sldf_workspace_size", "sldf_create", "sldf_destroy", "sldf_set_taps",
-                  "sldf_run", "sldf_run_batch", "sldf_lidar_quantize",
+                  "sldf_run", "sldf_run_batch", "sldf_lidar_quantize", "sldf_run_noalloc",
                   "sldf_timing_enable", "sldf_timing_read", "sldf_surrogate_set_weights",
                   "sldf_surrogate_forward", "sldf_surrogate_train_workspace_size",
                   "sldf_surrogate_train_step"):
@@ -276,6 +278,19 @@ class Context:
                                     disp.stride(0), _stream_handle(stream)),
                "sldf_run_batch")
         return disp, valid
+
+
+def run_noalloc(params: Params, left, right, lidar, disp, valid, stream=None):
+    """sldf_run_noalloc: one frame without a context or workspace (the
+    library's static per-GPU scratch); outputs are caller-provided device
+    tensors (disp float32 [H, W], valid uint8 [H, W])."""
+    for t in (left, right, lidar, disp, valid):
+        assert t.is_cuda and t.stride(-1) == 1
+    assert left.stride(0) == right.stride(0) and disp.stride(0) == valid.stride(0)
+    _check(lib().sldf_run_noalloc(ctypes.byref(params), _ptr(left), _ptr(right), left.stride(0),
+                                  _ptr(lidar), lidar.stride(0), _ptr(disp), _ptr(valid),
+                                  disp.stride(0), _stream_handle(stream)), "sldf_run_noalloc")
+    return disp, valid
 
 
 # ---------------------------------------------------------------- surrogate --

@@ -99,7 +99,7 @@ def test_workspace_size_plan():
     ("check_impl", 2, sldf.EINVAL),
     ("batch", 0, sldf.EINVAL),
     ("prior_cost", 3, sldf.EINVAL),
-    ("schedule", 3, sldf.EINVAL),
+    ("schedule", 4, sldf.EINVAL),
     ("huber_k", 0, sldf.EINVAL),
     ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
 ])
