@@ -396,7 +396,7 @@ def main():
 
     # learned check: same frames, right-view pass skipped unless a frame falls back
     learned = None
-    wpath = os.path.join(ROOT, "paper_2504_05148_amd", "weights", "surrogate_kitti.npz")
+    wpath = os.path.join(ROOT, "paper_2504_05148_amd", "weights", "surrogate_synthetic_1242x375.npz")
     if os.path.exists(wpath) and not args.no_learned:
         from paper_2504_05148_amd.train_surrogate import load_weights
         sw, sb, meta = load_weights(wpath)

@@ -72,8 +72,8 @@ typedef struct {
                               W * H * D <= 2^31 (one frame's cost volume is
                               addressed with 32-bit byte offsets) */
     int32_t census_w;      /* odd census window width  (<= 15) */
-    int32_t census_h;      /* odd census window height (<= 15);
-                              (census_w * census_h - 1) / 2 <= 32 bits */
+    int32_t census_h;      /* odd census window height (<= 15); at most 32
+                              code bits (see census_kind) */
     int32_t num_paths;     /* 4 (horizontal + vertical) or 8 (+ diagonals),
                               Sec. III; 1 = left-to-right only (debug) */
     int32_t p1, p2;        /* SGM penalties, Eq. 1-2 (Tab. II: 10, 120) */
@@ -135,6 +135,14 @@ typedef struct {
                               stream with events, so a call stays ordered
                               on the caller's stream and can be captured
                               into a graph */
+    int32_t census_kind;   /* census of the matching cost (Sec. IV-A):
+                              0 = centre-symmetric census (default): bit k =
+                              [I(p + o_k) > I(p - o_k)] over the first
+                              (w h - 1) / 2 window offsets in raster order;
+                              1 = full census: bit k = [I(p + o_k) < I(p)]
+                              over every offset but the centre in raster
+                              order, w h - 1 bits, which must be <= 32
+                              (e.g. 5 x 5: 24 bits; 9 x 7 is refused) */
 } sldf_params;
 
 /* Optional debug taps: device pointers, any may be NULL.  Written for frame
@@ -158,7 +166,18 @@ typedef struct {
      sweep_errors        int32  [1]      two-sweep schedule: nonzero if a wait
                                          for the row band above timed out (the
                                          results are then not valid); written
-                                         by every run of that schedule */
+                                         by every run of that schedule
+     cost                uint16 [H][W][D] joint cost C'(p, d) of the left view
+                                         (Eq. 4 scaled by alpha_den: (den - num)
+                                         H + num DDC), which the path passes
+                                         otherwise never store
+     path_cost           uint16 [H][W][D] L_r(p, d) of the left view for the one
+                                         direction path_dir (Eq. 2): 0 (+1, 0),
+                                         1 (-1, 0), 2 (0, +1), 3 (0, -1),
+                                         4 (+1, +1), 5 (-1, +1), 6 (+1, -1),
+                                         7 (-1, -1), as steps (dx, dy) from a
+                                         pixel's predecessor
+     path_dir            the direction of path_cost (0..7) */
 typedef struct {
     uint32_t* census_l;
     uint32_t* census_r;
@@ -170,6 +189,9 @@ typedef struct {
     uint16_t* rho;
     uint16_t* features;
     int32_t* sweep_errors;
+    uint16_t* cost;
+    uint16_t* path_cost;
+    int32_t path_dir;
 } sldf_taps;
 
 typedef struct sldf_ctx sldf_ctx;
@@ -211,7 +233,8 @@ sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_byt
    first. */
 sldf_status sldf_destroy(sldf_ctx* ctx);
 
-/* Set the debug taps written by subsequent runs (copied; NULL clears). */
+/* Set the debug taps written by subsequent runs (copied; NULL clears).
+   Errors: EINVAL (path_cost with path_dir outside 0..7). */
 sldf_status sldf_set_taps(sldf_ctx* ctx, const sldf_taps* taps);
 
 /* Process one frame (the whole method, Fig. 1 flow).  All pointers device:
@@ -321,6 +344,13 @@ sldf_status sldf_surrogate_forward(const uint16_t* x0, int32_t width, int32_t he
                                    int32_t n_frames, const uint16_t* weights,
                                    const float* biases, uint16_t* act1, uint16_t* act2,
                                    uint16_t* act3, float* logits, void* hip_stream);
+
+/* Working parameters from fp32 master parameters (device, num_weights +
+   num_biases floats, weights first): weights <- bf16 of the master weights
+   (round to nearest even), biases <- the master biases.  Enqueue-only.
+   Errors: EINVAL, EDEVICE. */
+sldf_status sldf_surrogate_sync_weights(const float* master, uint16_t* weights, float* biases,
+                                        void* hip_stream);
 
 /* Device workspace bytes of sldf_surrogate_train_step for F frames. */
 sldf_status sldf_surrogate_train_workspace_size(int32_t width, int32_t height,

@@ -80,13 +80,14 @@ class OracleParams:
     subpixel: int = 1
     prior_cost: int = 0
     huber_k: int = 1
+    census_kind: int = 0
 
 
 class _CParams(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int) for k in (
         "W", "H", "D", "cw", "ch", "num_paths", "p1", "p2", "q1", "q2", "a", "b",
         "blend_mode", "semidense", "ts", "rs", "tc", "rc", "check_mode",
-        "subpixel", "prior_cost", "huber_k")]
+        "subpixel", "prior_cost", "huber_k", "census_kind")]
 
 
 def _chk(rc):
@@ -94,8 +95,8 @@ def _chk(rc):
         raise RuntimeError(f"oracle returned status {rc}")
 
 
-def census_bits(cw: int, ch: int) -> int:
-    return (cw * ch - 1) // 2
+def census_bits(cw: int, ch: int, kind: int = 0) -> int:
+    return (cw * ch - 1) // 2 if kind == 0 else cw * ch - 1
 
 
 def quantize_lidar(lidar_f32: np.ndarray, D: int) -> np.ndarray:
@@ -106,11 +107,12 @@ def quantize_lidar(lidar_f32: np.ndarray, D: int) -> np.ndarray:
     return out
 
 
-def census(img: np.ndarray, cw: int, ch: int) -> np.ndarray:
+def census(img: np.ndarray, cw: int, ch: int, kind: int = 0) -> np.ndarray:
+    """kind 0: centre-symmetric census, 1: full census (sldf_oracle.c)."""
     a = np.ascontiguousarray(img, dtype=np.uint8)
     H, W = a.shape
     out = np.empty((H, W), np.uint32)
-    _chk(_load().orc_census(_p(a, u8), W, H, W, cw, ch, _p(out, u32)))
+    _chk(_load().orc_census_kind(_p(a, u8), W, H, W, cw, ch, kind, _p(out, u32)))
     return out
 
 
@@ -209,12 +211,12 @@ def lidar_residual(dstar, lidar, D, rc):
 
 
 def surrogate_features(S, dstar, rho, num_paths, P2s):
-    """float32 [H, W, 5] surrogate inputs (see sldf_oracle.c)."""
+    """float32 [H, W, 6] surrogate inputs (see sldf_oracle.c)."""
     s = np.ascontiguousarray(S, np.int32)
     H, W, D = s.shape
     ds = np.ascontiguousarray(dstar, np.int32)
     r = np.ascontiguousarray(rho, np.uint16)
-    out = np.empty((H, W, 5), np.float32)
+    out = np.empty((H, W, 6), np.float32)
     _chk(_load().orc_surrogate_features(_p(s, i32), _p(ds, i32), _p(r, ctypes.c_uint16),
                                         W, H, D, num_paths, P2s, _p(out, f32)))
     return out

@@ -67,11 +67,19 @@ int orc_quantize_lidar(const float* in, int W, int H, int D, int16_t* out)
 /* ------------------------------------------------------------------------ */
 int orc_census_bits(int cw, int ch) { return (cw * ch - 1) / 2; }
 
-int orc_census(const uint8_t* img, int W, int H, int pitch, int cw, int ch,
-               uint32_t* out)
+/* Census codes (Sec. IV-A cites the census of its matching cost).  kind 0:
+   the centre-symmetric census: the first n = (w h - 1) / 2 offsets o_k of
+   the window in raster order (the ones before the centre), bit k =
+   [I(p + o_k) > I(p - o_k)].  kind 1: the full census: every offset of the
+   window but the centre, in raster order, bit k = [I(p + o_k) < I(p)]
+   (w h - 1 bits, at most 32 here).  LSB first; 0 where the window leaves
+   the image. */
+int orc_census_kind(const uint8_t* img, int W, int H, int pitch, int cw, int ch, int kind,
+                    uint32_t* out)
 {
-    if (cw < 1 || ch < 1 || (cw % 2) == 0 || (ch % 2) == 0) return ORC_EINVAL;
-    int n = orc_census_bits(cw, ch);
+    if (cw < 1 || ch < 1 || (cw % 2) == 0 || (ch % 2) == 0 || kind < 0 || kind > 1)
+        return ORC_EINVAL;
+    int n = kind == 0 ? orc_census_bits(cw, ch) : cw * ch - 1;
     if (n > 32) return ORC_EINVAL;
     int rx = (cw - 1) / 2, ry = (ch - 1) / 2;
     for (int y = 0; y < H; ++y) {
@@ -79,14 +87,20 @@ int orc_census(const uint8_t* img, int W, int H, int pitch, int cw, int ch,
             uint32_t code = 0;
             if (x >= rx && x < W - rx && y >= ry && y < H - ry) {
                 int k = 0;
-                /* raster order over the window; the first n offsets are the
-                   ones before the centre */
                 for (int dy = -ry; dy <= ry && k < n; ++dy) {
                     for (int dx = -rx; dx <= rx && k < n; ++dx) {
                         int a = img[(y + dy) * pitch + (x + dx)];
-                        int b = img[(y - dy) * pitch + (x - dx)];
-                        if (a > b) code |= (1u << k);
-                        ++k;
+                        if (kind == 0) {
+                            /* raster order over the window; the first n
+                               offsets are the ones before the centre */
+                            int b = img[(y - dy) * pitch + (x - dx)];
+                            if (a > b) code |= (1u << k);
+                            ++k;
+                        } else {
+                            if (dx == 0 && dy == 0) continue;
+                            if (a < img[y * pitch + x]) code |= (1u << k);
+                            ++k;
+                        }
                     }
                 }
             }
@@ -94,6 +108,11 @@ int orc_census(const uint8_t* img, int W, int H, int pitch, int cw, int ch,
         }
     }
     return ORC_OK;
+}
+
+int orc_census(const uint8_t* img, int W, int H, int pitch, int cw, int ch, uint32_t* out)
+{
+    return orc_census_kind(img, W, H, pitch, cw, ch, 0, out);
 }
 
 static int popcount32(uint32_t v)
@@ -406,8 +425,14 @@ int orc_lidar_residual(const int32_t* dstar, const int16_t* lidar, int W, int H,
      f2 = S(d*-1) - 2 S(d*) + S(d*+1)    * sS   (0 at d* = 0 or D-1)
      f3 = d*                             * (1 / D)
      f4 = min(rho, 32)                   * (1 / 32)
+     f5 = v                              * (1 / 16), the occlusion margin of
+          the left disparity map: with q(x) = x - d*(x, y) the right-image
+          pixel that (x, y) matches and m = min of q(x') over the pixels
+          x' > x of the same row, v = q(x) - m clamped to [-16, 16]; v = 16
+          where q(x) < 0 (no matching pixel), v = -16 at the row end (no
+          pixel to the right)
    with sS = 1 / (num_paths * P2'); each product is one float32 multiply of
-   the integer by the float32 scale.  out is float [H][W][5]. */
+   the integer by the float32 scale.  out is float [H][W][6]. */
 int orc_surrogate_features(const int32_t* S, const int32_t* dstar, const uint16_t* rho,
                            int W, int H, int D, int num_paths, int P2s, float* out)
 {
@@ -426,11 +451,26 @@ int orc_surrogate_features(const int32_t* S, const int32_t* dstar, const uint16_
         int curv = 0;
         if (d > 0 && d < D - 1) curv = s[d - 1] - 2 * s[d] + s[d + 1];
         int r = rho[i] < 32 ? rho[i] : 32;
-        out[(size_t)i * 5 + 0] = (float)s[d] * sS;
-        out[(size_t)i * 5 + 1] = (float)second * sS;
-        out[(size_t)i * 5 + 2] = (float)curv * sS;
-        out[(size_t)i * 5 + 3] = (float)d * sD;
-        out[(size_t)i * 5 + 4] = (float)r * sR;
+        out[(size_t)i * 6 + 0] = (float)s[d] * sS;
+        out[(size_t)i * 6 + 1] = (float)second * sS;
+        out[(size_t)i * 6 + 2] = (float)curv * sS;
+        out[(size_t)i * 6 + 3] = (float)d * sD;
+        out[(size_t)i * 6 + 4] = (float)r * sR;
+    }
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const int q = x - dstar[y * W + x];
+            int m = 1 << 20;                 /* no pixel to the right */
+            for (int x2 = x + 1; x2 < W; ++x2) {
+                const int q2 = x2 - dstar[y * W + x2];
+                if (q2 < m) m = q2;
+            }
+            int v = q - m;
+            if (v < -16) v = -16;
+            if (v > 16) v = 16;
+            if (q < 0) v = 16;
+            out[((size_t)y * W + x) * 6 + 5] = (float)v * (1.0f / 16.0f);
+        }
     }
     return ORC_OK;
 }
@@ -455,6 +495,7 @@ typedef struct {
     int subpixel;
     int prior_cost;     /* 0 DDC, 1 quadratic, 2 Huber (orc_prior_penalty) */
     int huber_k;
+    int census_kind;    /* 0 centre-symmetric, 1 full census (orc_census_kind) */
 } orc_params;
 
 int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
@@ -465,7 +506,7 @@ int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
 {
     int W = P->W, H = P->H, D = P->D;
     size_t px = (size_t)W * H, cells = px * (size_t)D;
-    int n = orc_census_bits(P->cw, P->ch);
+    int n = P->census_kind == 1 ? P->cw * P->ch - 1 : orc_census_bits(P->cw, P->ch);
     int st = ORC_OK;
     uint32_t* cL = (uint32_t*)malloc(px * 4);
     uint32_t* cR = (uint32_t*)malloc(px * 4);
@@ -479,8 +520,10 @@ int orc_run(const orc_params* P, const uint8_t* left, const uint8_t* right,
         st = ORC_ENOMEM;
         goto done;
     }
-    if ((st = orc_census(left, W, H, img_pitch, P->cw, P->ch, cL))) goto done;
-    if ((st = orc_census(right, W, H, img_pitch, P->cw, P->ch, cR))) goto done;
+    if ((st = orc_census_kind(left, W, H, img_pitch, P->cw, P->ch, P->census_kind, cL)))
+        goto done;
+    if ((st = orc_census_kind(right, W, H, img_pitch, P->cw, P->ch, P->census_kind, cR)))
+        goto done;
     if (P->semidense)
         orc_semidense(cL, cR, lidar, W, H, n, P->ts, P->rs, prior);
     else

@@ -3,7 +3,7 @@ CPU.  Test infrastructure only (like the rest of this package): the HIP
 kernels are checked against it, never the other way round.
 
 The network is the one the library runs for check_impl = 1: four 3x3
-convolutions with dilations 1, 3, 9, 27 and channels 8 (5 used) -> 32 -> 32
+convolutions with dilations 1, 3, 9, 27 and channels 8 (6 used) -> 32 -> 32
 -> 32 -> 1, ReLU after the first three.  Inputs and weights are bf16 values;
 accumulation is fp32; the stored hidden activations are rounded to bf16 (round
 to nearest even), as the kernels store them.
@@ -18,6 +18,7 @@ LAYERS = [(32, 8, 1), (32, 32, 3), (32, 32, 9), (16, 32, 27)]   # (out_pad, in, 
 COUT = [32, 32, 32, 1]
 N_W = sum(9 * o * i for o, i, _ in LAYERS)
 N_B = 32 + 32 + 32 + 1
+N_IN = 6            # input channels in use (of 8): the six features of the library
 
 
 def bf16_bits_to_f32(bits: np.ndarray) -> np.ndarray:
@@ -25,8 +26,10 @@ def bf16_bits_to_f32(bits: np.ndarray) -> np.ndarray:
 
 
 def f32_to_bf16_bits(x: np.ndarray) -> np.ndarray:
-    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
-    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    """float32 -> bf16 bit patterns (round to nearest even): the oracle's
+    pinned rounding."""
+    from oracle import bf16_round
+    return bf16_round(x)
 
 
 def round_bf16(t: torch.Tensor) -> torch.Tensor:
@@ -52,7 +55,7 @@ def init_params(seed: int = 0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     w = np.zeros(N_W, np.float32)
     off = 0
-    for (oc, ic, _), cout, cin_used in zip(LAYERS, COUT, [5, 32, 32, 32]):
+    for (oc, ic, _), cout, cin_used in zip(LAYERS, COUT, [N_IN, 32, 32, 32]):
         blk = np.zeros((9, oc, ic), np.float32)
         bound = np.sqrt(6.0 / (9 * cin_used))
         blk[:, :cout, :cin_used] = rng.uniform(-bound, bound, size=(9, cout, cin_used))

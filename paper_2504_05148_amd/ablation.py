@@ -176,7 +176,7 @@ def table(title: str, rows: dict) -> str:
 
 def _load_surrogate():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
-                        "surrogate_kitti.npz")
+                        "surrogate_synthetic_1242x375.npz")
     if not os.path.exists(path):
         return None
     from paper_2504_05148_amd.train_surrogate import load_weights

@@ -212,6 +212,52 @@ hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s)
     return hipGetLastError();
 }
 
+// Occlusion margin of the left disparity map, the sixth learned-check input:
+// for pixel (x, y) with d = d*, m = min over x' > x of x' - d*(x', y) (the
+// leftmost right-image pixel that the pixels to its right map to) and
+// v = (x - d) - m, clamped to [-16, 16] (16 where x - d < 0: no matching
+// pixel; -16 at the row end); the input is v / 16.  v >= 0 means that a
+// pixel further right lands on or left of this pixel's match, as around
+// occlusions.  One wave per row: each lane takes a run of pixels, the runs'
+// minima are combined right to left across the wave, then each lane walks
+// its run from right to left.
+__global__ __launch_bounds__(256) void occlusion_kernel(const int16_t* dstar, uint16_t* x0, int W,
+                                                        int H, int64_t px_stride)
+{
+    const int lane = threadIdx.x & 63;
+    const int y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (y >= H) return;                          // uniform over the wave
+    const int64_t row = (int64_t)blockIdx.y * px_stride + (int64_t)y * W;
+    const int seg = (W + 63) / 64;
+    const int lo = min(lane * seg, W), hi = min(lo + seg, W);
+    constexpr int kNone = 1 << 20;               // no pixel to the right
+    int run_min = kNone;
+    for (int x = lo; x < hi; ++x) run_min = min(run_min, x - (int)dstar[row + x]);
+    // minimum over the runs of the lanes to the right (exclusive)
+    int incl = run_min;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_down(incl, o, 64);
+        incl = lane + o < 64 ? min(incl, v) : incl;
+    }
+    const int excl = __shfl_down(incl, 1, 64);
+    int m = lane < 63 ? excl : kNone;
+    for (int x = hi - 1; x >= lo; --x) {
+        const int q = x - (int)dstar[row + x];
+        const int v = q < 0 ? 16 : max(-16, min(16, q - m));
+        x0[(row + x) * 8 + 5] = f32_to_bf16_rne((float)v * (1.0f / 16.0f));
+        m = min(m, q);
+    }
+}
+
+hipError_t launch_occlusion(const int16_t* dstar, uint16_t* x0, int W, int H, int64_t px_stride,
+                            int nframes, hipStream_t s)
+{
+    hipLaunchKernelGGL(occlusion_kernel, dim3((H + 3) / 4, nframes), dim3(256), 0, s, dstar, x0,
+                       W, H, px_stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_lidar_rho(const LidarArgs& a0, int nframes, hipStream_t s)
 {
     if (!a0.wmask || !a0.dstar || !a0.rho || (a0.x0 && !a0.feat)) return hipErrorInvalidValue;

@@ -52,7 +52,8 @@ template <int CWT, int CHT>
 __global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
 {
     const int cw = CWT ? CWT : a.cw, ch = CHT ? CHT : a.ch;
-    const int rx = (cw - 1) / 2, ry = (ch - 1) / 2, n = (cw * ch - 1) / 2;
+    const int rx = (cw - 1) / 2, ry = (ch - 1) / 2;
+    const int n = a.kind == 1 ? cw * ch - 1 : (cw * ch - 1) / 2;
     __shared__ __align__(16) uint8_t tile[kCensusLH][kCensusLW];
     const int view = blockIdx.z & 1, frame = blockIdx.z >> 1;
     const uint8_t* img = (view ? a.right : a.left) + (int64_t)frame * a.img_fstride;
@@ -117,16 +118,29 @@ __global__ __launch_bounds__(256) void census_kernel(CensusArgs a)
         if (x >= rx && x < a.W - rx && y >= ry && y < a.H - ry) {
             const int cy = ry + ty, cx = 16 + lx;
             int k = 0;
-#pragma unroll
-            for (int dy = -ry; dy <= ry; ++dy) {
-#pragma unroll
-                for (int dx = -rx; dx <= rx; ++dx) {
-                    if (k < n) {
-                        uint32_t p = tile[cy + dy][cx + dx];
-                        uint32_t q = tile[cy - dy][cx - dx];
-                        code |= (uint32_t)(p > q) << k;
+            if (a.kind == 1) {
+                // full census: every offset but the centre, raster order,
+                // bit k = [I(p + o_k) < I(p)]
+                const uint32_t c = tile[cy][cx];
+                for (int dy = -ry; dy <= ry; ++dy) {
+                    for (int dx = -rx; dx <= rx; ++dx) {
+                        if (dx == 0 && dy == 0) continue;
+                        code |= (uint32_t)(tile[cy + dy][cx + dx] < c) << k;
+                        ++k;
                     }
-                    ++k;
+                }
+            } else {
+#pragma unroll
+                for (int dy = -ry; dy <= ry; ++dy) {
+#pragma unroll
+                    for (int dx = -rx; dx <= rx; ++dx) {
+                        if (k < n) {
+                            uint32_t p = tile[cy + dy][cx + dx];
+                            uint32_t q = tile[cy - dy][cx - dx];
+                            code |= (uint32_t)(p > q) << k;
+                        }
+                        ++k;
+                    }
                 }
             }
         }
@@ -138,7 +152,9 @@ hipError_t launch_census(const CensusArgs& a, int nframes, hipStream_t s)
 {
     dim3 grid((a.W + kCensusTW - 1) / kCensusTW, (a.H + kCensusTH - 1) / kCensusTH,
               2 * nframes);
-    if (a.cw == 9 && a.ch == 7)
+    if (a.kind == 1)
+        hipLaunchKernelGGL((census_kernel<0, 0>), grid, dim3(256), 0, s, a);
+    else if (a.cw == 9 && a.ch == 7)
         hipLaunchKernelGGL((census_kernel<9, 7>), grid, dim3(256), 0, s, a);
     else if (a.cw == 5 && a.ch == 5)
         hipLaunchKernelGGL((census_kernel<5, 5>), grid, dim3(256), 0, s, a);

@@ -221,6 +221,39 @@ static hipError_t launch_dir(const SgmArgs& a0, int D, int mode, int nviews, int
     return hipGetLastError();
 }
 
+// Joint cost tap: C'(p, d) of frame 0's left view for every pixel, computed
+// as the path passes compute it (cost_lane) and stored as [H][W][D] u16.
+// G lanes per pixel, each with 8 disparities.
+template <int G>
+__global__ __launch_bounds__(256) void cost_tap_kernel(SgmArgs a, uint16_t* out)
+{
+    constexpr int D = G * 8;
+    __shared__ uint32_t pat[pattern_words(D)];
+    build_pattern<D>(a, pat);
+    __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+    if (q >= (int64_t)a.W * a.H) return;
+    const int g = threadIdx.x % G, d0 = 8 * g;
+    const int y = (int)(q / a.W), x = (int)(q - (int64_t)y * a.W);
+    const LineAddr la = line_addr<D, 0>(a, 0, 0, y, d0, 1, 0, a.S[0]);
+    StepIn<4> in;
+    load_pixel<0>(la, la.at(x), in);
+    uint32_t C[4];
+    cost_lane<D, 0>(a, reinterpret_cast<const char*>(pat) + 2 * d0, in, x, d0, C);
+    *reinterpret_cast<u32x4*>(out + q * D + d0) = pack_v<4>(C);
+}
+
+hipError_t launch_cost_tap(const SgmArgs& a, int D, uint16_t* out, hipStream_t s)
+{
+    const int G = D / 8;
+    const int64_t n = (int64_t)a.W * a.H;
+    dim3 grid((unsigned)((n + 256 / G - 1) / (256 / G)));
+    if (G == 8) hipLaunchKernelGGL(cost_tap_kernel<8>, grid, dim3(256), 0, s, a, out);
+    else if (G == 16) hipLaunchKernelGGL(cost_tap_kernel<16>, grid, dim3(256), 0, s, a, out);
+    else hipLaunchKernelGGL(cost_tap_kernel<32>, grid, dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_sgm_dir(const SgmArgs& a, int D, int mode, int nviews, int nframes,
                           hipStream_t s)
 {

@@ -540,6 +540,27 @@ __global__ void adam_kernel(AdamArgs a)
         a.bias[i - a.n_w] = p;
 }
 
+// Working parameters from the fp32 master copy: bf16 weights (RNE) and fp32
+// biases, the form the convolutions read.
+__global__ void sync_weights_kernel(const float* master, int n_w, int n, uint16_t* w_bf16,
+                                    float* bias)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i < n_w)
+        w_bf16[i] = bf16_rne(master[i]);
+    else
+        bias[i - n_w] = master[i];
+}
+
+hipError_t launch_sync_weights(const float* master, uint16_t* w_bf16, float* bias, hipStream_t s)
+{
+    const int n = kSurNW + kSurNB;
+    hipLaunchKernelGGL(sync_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, s, master, kSurNW,
+                       n, w_bf16, bias);
+    return hipGetLastError();
+}
+
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(adam_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);

@@ -40,6 +40,14 @@ namespace {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Bits of a census code: (w h - 1) / 2 centre-symmetric pairs, or w h - 1
+// for the full census.
+int census_bits(const sldf_params* p)
+{
+    const int wh = p->census_w * p->census_h;
+    return p->census_kind == 1 ? wh - 1 : (wh - 1) / 2;
+}
+
 // Largest joint cost C' = (den - num) H + num DDC, or den H without prior in
 // blend mode 1 (Eq. 4 scaled by den).
 int64_t max_cost(const sldf_params* p, int n)
@@ -61,7 +69,8 @@ sldf_status validate(const sldf_params* p)
     if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1) ||
         p->census_w > 15 || p->census_h > 15)
         return SLDF_EINVAL;
-    int n = (p->census_w * p->census_h - 1) / 2;
+    if (p->census_kind != 0 && p->census_kind != 1) return SLDF_EINVAL;
+    int n = census_bits(p);
     if (n < 1 || n > 32) return SLDF_EINVAL;
     if (p->num_paths != 1 && p->num_paths != 4 && p->num_paths != 8) return SLDF_EINVAL;
     if (p->p1 < 0 || p->p2 < p->p1 || p->q1 < 0 || p->q2 < p->q1) return SLDF_EINVAL;
@@ -268,6 +277,7 @@ void sldf_params_default(sldf_params* p)
     p->prior_cost = 0;    // DDC
     p->huber_k = 1;
     p->schedule = 0;      // automatic
+    p->census_kind = 0;   // centre-symmetric census
 }
 
 sldf_status sldf_workspace_size(const sldf_params* p, size_t* bytes)
@@ -299,7 +309,7 @@ sldf_status sldf_create(const sldf_params* p, void* dev_workspace, size_t ws_byt
     c->device = dev;
     plan(p, (char*)dev_workspace, &c->buf);
     c->need_right = needs_right(p);
-    c->n = (p->census_w * p->census_h - 1) / 2;
+    c->n = census_bits(p);
     if (c->buf.S3[0]) {
         // default priority; non-blocking w.r.t. the null stream (the events
         // order it against the caller's stream)
@@ -388,6 +398,7 @@ sldf_status sldf_timing_read(sldf_ctx* ctx, double* ms, int64_t* launches)
 sldf_status sldf_set_taps(sldf_ctx* ctx, const sldf_taps* taps)
 {
     if (!ctx) return SLDF_EINVAL;
+    if (taps && taps->path_cost && (taps->path_dir < 0 || taps->path_dir > 7)) return SLDF_EINVAL;
     if (taps)
         ctx->taps = *taps;
     else
@@ -452,6 +463,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     ca.H = H;
     ca.cw = p.census_w;
     ca.ch = p.census_h;
+    ca.kind = p.census_kind;
     if ((e = launch_census(ca, n_frames, s)) != hipSuccess) return SLDF_EDEVICE;
     if (mark(1) != hipSuccess) return SLDF_EDEVICE;
     ctx->launches[0] += 1;
@@ -694,6 +706,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     } else if ((e = launch_lidar_bits(la, n_frames, s)) != hipSuccess) {
         return SLDF_EDEVICE;
     }
+    if (la.x0 && launch_occlusion(b.dstar, b.x0, W, H, b.px_stride, n_frames, s) != hipSuccess)
+        return SLDF_EDEVICE;
 
     // stereo-LiDAR consistency check (Sec. IV-C, Eq. 6)
     CheckArgs ka;
@@ -794,6 +808,24 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
     if (cp(t.rho, b.rho, px * 2) != hipSuccess || cp(t.features, b.x0, px * 16) != hipSuccess)
         return SLDF_EDEVICE;
     if (b.sync && cp(t.sweep_errors, b.sync + 2, 4) != hipSuccess) return SLDF_EDEVICE;
+    // joint cost and one direction's path cost of frame 0 (left view): the
+    // passes never store them, so they are recomputed here from the census
+    // and prior words of the run
+    if (t.cost || t.path_cost) {
+        SgmArgs gt = ga;
+        gt.gate = nullptr;
+        gt.feat = nullptr;
+        gt.store_sum = 0;
+        gt.view_base = 0;
+        if (t.cost && launch_cost_tap(gt, D, t.cost, s) != hipSuccess) return SLDF_EDEVICE;
+        if (t.path_cost) {
+            gt.S[0] = t.path_cost;
+            gt.dx = kDirs[t.path_dir][0];
+            gt.dy = kDirs[t.path_dir][1];
+            gt.nlines = num_lines(W, H, gt.dx, gt.dy);
+            if (launch_sgm_dir(gt, D, kFirst, 1, 1, s) != hipSuccess) return SLDF_EDEVICE;
+        }
+    }
     return SLDF_OK;
 }
 
@@ -865,7 +897,7 @@ sldf_status sldf_run_noalloc(const sldf_params* params, const uint8_t* left,
     c.device = dev;
     plan(&p, ws, &c.buf);
     c.need_right = needs_right(&p);
-    c.n = (p.census_w * p.census_h - 1) / 2;
+    c.n = census_bits(&p);
     return sldf_run_batch(&c, 1, left, right, img_pitch, 0, lidar, lidar_pitch, 0, disp_out,
                           valid_out, out_pitch, 0, hip_stream);
 }
@@ -977,6 +1009,15 @@ sldf_status sldf_surrogate_forward(const uint16_t* x0, int32_t width, int32_t he
     uint16_t* const act[3] = {act1, act2, act3};
     return surrogate_forward(x0, width, height, n_frames, weights, biases, act, logits,
                              (hipStream_t)hip_stream) == hipSuccess
+               ? SLDF_OK
+               : SLDF_EDEVICE;
+}
+
+sldf_status sldf_surrogate_sync_weights(const float* master, uint16_t* weights, float* biases,
+                                        void* hip_stream)
+{
+    if (!master || !weights || !biases) return SLDF_EINVAL;
+    return launch_sync_weights(master, weights, biases, (hipStream_t)hip_stream) == hipSuccess
                ? SLDF_OK
                : SLDF_EDEVICE;
 }

@@ -64,6 +64,7 @@ struct CensusArgs {
     int32_t out_pitch;
     int64_t out_fstride;
     int32_t W, H, cw, ch;
+    int32_t kind;            // 0 centre-symmetric census, 1 full census
 };
 
 // Prior word of a pixel: what the path passes need of the prior e_p of the
@@ -267,6 +268,7 @@ hipError_t launch_reduce_wgrad(const float* pw, const float* pb, int nblocks, in
                                int oc_valid, float* gw, float* gb, hipStream_t s);
 hipError_t launch_bce(const LossArgs& a, int nframes, hipStream_t s);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
+hipError_t launch_sync_weights(const float* master, uint16_t* w_bf16, float* bias, hipStream_t s);
 hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s);
 
@@ -291,6 +293,8 @@ hipError_t launch_sgm_dual(const SgmArgs& a, int D, int mode, int nviews, int nf
                            hipStream_t s, int k = 8);
 // split schedule: winner-takes-all (+ subpixel) on S + S2 of every pixel
 hipError_t launch_sgm_wta(const SgmArgs& a, int D, int nviews, int nframes, hipStream_t s);
+// debug tap: C'(p, d) of frame 0, left view, [H][W][D]
+hipError_t launch_cost_tap(const SgmArgs& a, int D, uint16_t* out, hipStream_t s);
 // runs of at most this many frames use the split schedule
 constexpr int kSplitFrames = 1;
 
@@ -314,6 +318,9 @@ hipError_t launch_check(const CheckArgs& a, int nframes, hipStream_t s);
 hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s);
 // residual + surrogate inputs from a.wmask (masks of launch_lidar_bits with wmask)
 hipError_t launch_lidar_rho(const LidarArgs& a, int nframes, hipStream_t s);
+// sixth learned-check input (occlusion margin of d*) into x0 channel 5
+hipError_t launch_occlusion(const int16_t* dstar, uint16_t* x0, int W, int H, int64_t px_stride,
+                            int nframes, hipStream_t s);
 hipError_t launch_quantize(const float* in, int W, int H, int in_pitch, int D,
                            int16_t* out, int out_pitch, hipStream_t s);
 

@@ -25,7 +25,7 @@ _PARAM_FIELDS = ("struct_size", "width", "height", "max_disp", "census_w", "cens
 
 
 _PARAM_FLOATS = ("fallback_tau", "uncertain_margin")
-_PARAM_TAIL = ("prior_cost", "huber_k", "schedule")     # int32 fields after the floats
+_PARAM_TAIL = ("prior_cost", "huber_k", "schedule", "census_kind")   # int32 after the floats
 
 
 class Params(ctypes.Structure):
@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
 class Taps(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in
                 ("census_l", "census_r", "prior", "cost_sum", "dstar", "dright", "dsub",
-                 "rho", "features", "sweep_errors")]
+                 "rho", "features", "sweep_errors", "cost", "path_cost")] + [
+                ("path_dir", ctypes.c_int32)]
 
 
 class SldfError(RuntimeError):
@@ -88,6 +89,7 @@ def lib():
                                              _vp, _vp]
         L.sldf_surrogate_train_workspace_size.argtypes = [_i32, _i32, _i32,
                                                           ctypes.POINTER(_sz)]
+        L.sldf_surrogate_sync_weights.argtypes = [_vp, _vp, _vp, _vp]
         _f = ctypes.c_float
         L.sldf_surrogate_train_step.argtypes = [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp,
                                                 _vp, _vp, _vp, _vp, _f, _f, _f, _f, _i32,
@@ -96,6 +98,7 @@ def lib():
                   "sldf_run", "sldf_run_batch", "sldf_lidar_quantize", "sldf_run_noalloc",
                   "sldf_timing_enable", "sldf_timing_read", "sldf_surrogate_set_weights",
                   "sldf_surrogate_forward", "sldf_surrogate_train_workspace_size",
+                  "sldf_surrogate_sync_weights",
                   "sldf_surrogate_train_step"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -208,11 +211,15 @@ class Context:
 
     def set_taps(self, **tensors):
         """Debug taps (frame 0): census_l, census_r, prior, cost_sum, dstar,
-        dright, dsub, rho, features -> device tensors of the documented
-        dtypes."""
+        dright, dsub, rho, features, sweep_errors, cost, path_cost -> device
+        tensors of the documented dtypes; path_dir (int) picks the direction
+        of path_cost."""
         t = Taps()
         for k, v in tensors.items():
-            setattr(t, k, _ptr(v) if v is not None else None)
+            if k == "path_dir":
+                t.path_dir = int(v)
+            else:
+                setattr(t, k, _ptr(v) if v is not None else None)
         self._taps_keep = dict(tensors)
         _check(lib().sldf_set_taps(self._h, ctypes.byref(t)), "sldf_set_taps")
 
@@ -338,13 +345,12 @@ class SurrogateTrainer:
         self.step_count = 0
         self.stats = torch.zeros(4, dtype=torch.float32, device=device)
 
-    def sync_working(self):
-        """bf16 (round to nearest even) working weights from the master copy."""
-        w = self.master[:self.nw]
-        u = w.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
-        u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-        self.weights.copy_(u.to(torch.int32).to(torch.int16))
-        self.biases.copy_(self.master[self.nw:])
+    def sync_working(self, stream=None):
+        """Working parameters (bf16 weights, fp32 biases) from the master copy,
+        by the library (sldf_surrogate_sync_weights)."""
+        _check(lib().sldf_surrogate_sync_weights(_ptr(self.master), _ptr(self.weights),
+                                                 _ptr(self.biases), _stream_handle(stream)),
+               "sldf_surrogate_sync_weights")
 
     def step(self, x0, labels, rho, tc, update=True, grads_out=None, stream=None):
         F = x0.shape[0]

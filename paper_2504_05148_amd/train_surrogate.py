@@ -22,7 +22,9 @@ from multiprocessing import Pool
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_OUT = os.path.join(HERE, "weights", "surrogate_kitti.npz")
+# trained on the synthetic paper-scale frames of the surrogate workload (no
+# KITTI data is involved)
+DEFAULT_OUT = os.path.join(HERE, "weights", "surrogate_synthetic_1242x375.npz")
 
 
 def _gen(idx):
@@ -49,7 +51,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--heldout", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--workers", type=int, default=14)
@@ -58,7 +60,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     import torch
-    from paper_2504_05148_amd import sldf
+    from paper_2504_05148_amd import sldf, synth
 
     torch.cuda.set_device(0)
     W, H, D = 1242, 375, 128
@@ -97,7 +99,7 @@ def main(argv=None):
     master = np.zeros(nw + nb, np.float32)
     off = 0
     for (oc, ic), cout, cin_used in zip([(32, 8), (32, 32), (32, 32), (16, 32)],
-                                        [32, 32, 32, 1], [5, 32, 32, 32]):
+                                        [32, 32, 32, 1], [6, 32, 32, 32]):
         blk = np.zeros((9, oc, ic), np.float32)
         bound = np.sqrt(6.0 / (9 * cin_used))
         blk[:, :cout, :cin_used] = rng.uniform(-bound, bound, size=(9, cout, cin_used))
@@ -136,7 +138,9 @@ def main(argv=None):
     undecided = (rho[args.train:].to(torch.int32) & 0xFFFF) > p.tc   # uint16 bits
     lab_h = lab[args.train:].bool()
     learned = (z > 0) | ~undecided
-    agree_f = (learned == lab_h).flatten(1).float().mean(1).cpu().numpy()
+    # per-frame agreement from exact pixel counts
+    agree_f = ((learned == lab_h).flatten(1).sum(1).cpu().numpy().astype(np.float64) /
+               float(W * H))
     sweep = []
     for margin in (0.25, 0.5, 1.0, 2.0):
         unc = ((z.abs() < margin) & undecided).flatten(1).sum(1).cpu().numpy() / (W * H)
@@ -188,10 +192,36 @@ def main(argv=None):
                          coverage_plain=cov_p / (args.heldout * W * H))
         _log(f"held-out {name}: {res[name]}")
 
+    # the two routes to the no-fallback agreement (one batched forward over
+    # the held-out inputs, and per-frame learned runs) must agree exactly
+    nf = res["no_fallback"]["agreement"]
+    if abs(nf - float(agree_f.mean())) > 1e-9:
+        raise RuntimeError(f"held-out agreement differs between the batched forward "
+                           f"({agree_f.mean():.6f}) and the learned runs ({nf:.6f})")
+
+    # the benchmark's frames (paper-scale workload, frames 0..63): learned
+    # (no fallback) against plain masks in one batched call each
+    nb = 64
+    bframes = [synth.kitti_frame(i) for i in range(nb)]
+    bl = sldf.device_images(np.stack([f["left"] for f in bframes]))
+    br = sldf.device_images(np.stack([f["right"] for f in bframes]))
+    blq = torch.stack([sldf.quantize_lidar(torch.from_numpy(f["lidar"]).cuda(), D)
+                       for f in bframes])
+    _, vp = sldf.Context(sldf.default_params(batch=nb)).run_batch(bl, br, blq)
+    cb = sldf.Context(sldf.default_params(batch=nb, check_impl=1, fallback_tau=1.0,
+                                          uncertain_margin=0.0))
+    cb.set_surrogate(tr.weights, tr.biases)
+    _, vl = cb.run_batch(bl, br, blq)
+    bench_agree = float((vl == vp).float().mean().item())
+    _log(f"bench frames (0..{nb - 1}) agreement without fallback {bench_agree:.5f}")
+
     meta = dict(train_frames=args.train, heldout_frames=args.heldout, epochs=args.epochs,
                 batch=args.batch, lr=args.lr, seed=args.seed, workload="1242x375 D=128 "
                 "synthetic paper-scale frames (config id 4)", eval=res,
-                fallback_sweep=sweep, tuned=best)
+                fallback_sweep=sweep, tuned=best,
+                heldout_agreement_batched_forward=float(agree_f.mean()),
+                bench_frames_agreement=bench_agree,
+                inputs="S(d*), second minimum, curvature, d*, LiDAR residual, occlusion margin")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.savez(args.out, master=tr.master.cpu().numpy(),
              weight_bits=tr.weights.cpu().numpy().view(np.uint16),

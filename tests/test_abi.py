@@ -101,6 +101,8 @@ def test_workspace_size_plan():
     ("prior_cost", 3, sldf.EINVAL),
     ("schedule", 4, sldf.EINVAL),
     ("huber_k", 0, sldf.EINVAL),
+    ("census_kind", 2, sldf.EINVAL),
+    ("census_kind", 1, sldf.EINVAL),   # full census of the default 9 x 7 window: 62 bits
     ("p2", 2000, sldf.EOVERFLOW),       # 8 paths * (C' + P2') >= 65536
 ])
 def test_validation(field, value, status):
@@ -156,3 +158,20 @@ def test_status_strings():
     for s in range(-7, 1):
         assert sldf.status_string(s)
     assert sldf.status_string(-99) == "unknown status"
+
+
+def test_full_census_parameters():
+    # 5 x 5 full census: 24 bits, valid; the bound uses the larger bit count
+    assert sldf.workspace_size(sldf.default_params(census_kind=1, census_w=5, census_h=5)) > 0
+    assert sldf.default_params().census_kind == 0
+
+
+def test_taps_struct_matches_header():
+    """sldf_taps: twelve device pointers then the int32 direction of the
+    single-path tap, in the header's order."""
+    src = open(HEADER).read()
+    body = src[:src.index("} sldf_taps;")].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b(\w+);", body)
+    assert fields == [f for f, _ in sldf.Taps._fields_]
+    assert sldf.Taps.path_dir.offset == 12 * ctypes.sizeof(ctypes.c_void_p)

@@ -29,7 +29,7 @@ def _oracle_params(p: dict) -> oracle.OracleParams:
         semidense=p.get("semidense", 1), ts=p.get("ts", 2), rs=p.get("rs", 6),
         tc=p.get("tc", 2), rc=p.get("rc", 20), check_mode=p.get("check_mode", 3),
         subpixel=p.get("subpixel", 1), prior_cost=p.get("prior_cost", 0),
-        huber_k=p.get("huber_k", 1))
+        huber_k=p.get("huber_k", 1), census_kind=p.get("census_kind", 0))
 
 
 def run_gpu(frame, pkw, taps=True):
@@ -80,7 +80,7 @@ def run_oracle(frame, pkw):
     r["rho"] = oracle.lidar_residual(r["dstar"], lid, op.D, op.rc)
     f = oracle.surrogate_features(r["S"], r["dstar"], r["rho"], op.num_paths, op.b * op.p2)
     feats = np.zeros(f.shape[:2] + (8,), np.uint16)
-    feats[..., :5] = oracle.bf16_round(f)
+    feats[..., :6] = oracle.bf16_round(f)
     r["features"] = feats
     return r
 
@@ -189,6 +189,8 @@ def test_ragged_shapes(W, H, D, paths):
     dict(census_w=7, census_h=7), dict(census_w=3, census_h=9), dict(p1=0, p2=0),
     dict(prior_cost=1), dict(prior_cost=1, q2=980), dict(prior_cost=2, huber_k=1),
     dict(prior_cost=2, huber_k=3, q2=980),
+    # the full census (24 and 26 bits)
+    dict(census_kind=1), dict(census_kind=1, census_w=3, census_h=9),
 ])
 def test_parameter_variants(extra):
     f = synth.small_frame(4)
@@ -340,3 +342,75 @@ def test_workload_shapes(name, schedule):
     f, pkw, o = _workload_case(name)
     print(f"case workload {name} schedule={schedule}", flush=True)
     assert_parity(run_gpu(f, dict(pkw, schedule=schedule)), o, pkw)
+
+
+def _cost_path_taps(f, pkw, dirs):
+    """Run with the C' and L_r taps; return the GPU volumes and the oracle's
+    (from the oracle's own census codes and prior map)."""
+    p = sldf.default_params(**pkw)
+    W, H, D = p.width, p.height, p.max_disp
+    op = _oracle_params(p.as_dict() | pkw)
+    o = run_oracle(f, pkw)
+    n = oracle.census_bits(op.cw, op.ch, op.census_kind)
+    prior = o["prior"]
+    cost = oracle.joint_cost(o["census_l"], o["census_r"], prior, D, n, 0, op.a, op.b, op.q1,
+                             op.q2, op.blend_mode, op.prior_cost, op.huber_k)
+    ctx = sldf.Context(p)
+    left = sldf.device_image(f["left"])
+    right = sldf.device_image(f["right"])
+    lid_q = sldf.quantize_lidar(torch.from_numpy(np.ascontiguousarray(f["lidar"])).cuda(), D)
+    results = []
+    for k in dirs:
+        tc = torch.empty((H, W, D), dtype=torch.int16, device="cuda")
+        tl = torch.empty((H, W, D), dtype=torch.int16, device="cuda")
+        ctx.set_taps(cost=tc, path_cost=tl, path_dir=k)
+        ctx.run(left, right, lid_q)
+        torch.cuda.synchronize()
+        dx, dy = oracle.direction(k)
+        exp_l = oracle.path(cost, dx, dy, op.b * op.p1, op.b * op.p2)
+        results.append((k, tc.cpu().numpy().view(np.uint16), tl.cpu().numpy().view(np.uint16),
+                        exp_l))
+    ctx.close()
+    return cost, results
+
+
+@pytest.mark.parametrize("extra", [dict(), dict(census_kind=1), dict(prior_cost=2, huber_k=2),
+                                   dict(blend_mode=1, schedule=3)])
+def test_cost_and_single_path_taps_small(extra):
+    """C'(p, d) (Eq. 4) and L_r(p, d) (Eq. 2) of each of the eight
+    directions, bit-exact against the oracle."""
+    f = synth.small_frame(1)
+    pkw = _params(f["W"], f["H"], f["D"], **SMALL)
+    pkw.update(extra)
+    print(f"case cost/path taps small {extra}", flush=True)
+    cost, res = _cost_path_taps(f, pkw, range(8))
+    for k, gc, gl, el in res:
+        assert (gc.astype(np.int64) == cost).all(), f"C' mismatch at {np.argwhere(gc != cost)[:5]}"
+        bad = gl.astype(np.int64) != el
+        assert not bad.any(), f"L_r dir {k} mismatch at {np.argwhere(bad)[:5]}"
+
+
+@pytest.mark.parametrize("W,H,D", [(1242, 375, 128), (301, 40, 256), (97, 31, 64)])
+def test_cost_and_single_path_taps_shapes(W, H, D):
+    if W == 1242:
+        f = synth.kitti_frame(2)
+    else:
+        f = synth.make_frame(synth.robust_spec(W=W, H=H, D=D, density=0.05, lines=16), 3, W + H)
+    pkw = _params(W, H, D)
+    dirs = [0, 5] if W == 1242 else [1, 2, 7]
+    print(f"case cost/path taps {W}x{H} D={D} dirs={dirs}", flush=True)
+    cost, res = _cost_path_taps(f, pkw, dirs)
+    for k, gc, gl, el in res:
+        assert (gc.astype(np.int64) == cost).all(), "C' mismatch"
+        assert (gl.astype(np.int64) == el).all(), f"L_r dir {k} mismatch"
+
+
+def test_path_tap_direction_out_of_range_is_rejected():
+    p = sldf.default_params(width=64, height=16, max_disp=64)
+    ctx = sldf.Context(p)
+    t = torch.empty((16, 64, 64), dtype=torch.int16, device="cuda")
+    for bad in (-1, 8):
+        with pytest.raises(sldf.SldfError):
+            ctx.set_taps(path_cost=t, path_dir=bad)
+    ctx.set_taps(path_cost=t, path_dir=7)
+    ctx.close()

@@ -40,40 +40,126 @@ def _params_bits(seed=0, bias_scale=0.1):
 def _random_x0(F, H, W, seed):
     rng = np.random.default_rng(seed)
     x = np.zeros((F, H, W, 8), np.float32)
-    x[..., :5] = rng.uniform(0, 1, size=(F, H, W, 5))
+    x[..., :ref.N_IN] = rng.uniform(0, 1, size=(F, H, W, ref.N_IN))
     return ref.f32_to_bf16_bits(x)
+
+
+U32 = 2.0 ** -24          # fp32 unit roundoff
+
+
+def _nchw(bits_nhwc):
+    """bf16 bits [F, H, W, C] -> float32 torch [F, C, H, W]."""
+    return torch.from_numpy(ref.bf16_bits_to_f32(bits_nhwc)).permute(0, 3, 1, 2).contiguous()
+
+
+def _layer(x, w, b, dil):
+    """One convolution of the reference in fp32 (value) and on |x|, |w| (the
+    sum of the absolute terms, for the accumulation error bound)."""
+    y = torch.nn.functional.conv2d(x, w, b, padding=dil, dilation=dil)
+    a = torch.nn.functional.conv2d(x.abs(), w.abs(), b.abs(), padding=dil, dilation=dil)
+    return y, a
+
+
+def _bf16(t):
+    return ref.f32_to_bf16_bits(t.numpy())
+
+
+def _check_layer_output(g_bits, y, a, n_terms, relu, what):
+    """GPU bf16 output vs the fp32 reference value y of the same inputs: the
+    two sums differ only in their order, by at most gamma_n * sum|terms|
+    (gamma_n = n u / (1 - n u)); so the GPU value must be the bf16 rounding
+    of some value in [y - tol, y + tol]: rounding is monotonic, so it lies
+    between the roundings of the two interval ends (where the terms cancel,
+    the interval can span several bf16 steps), and it equals the rounding
+    of y wherever the interval holds no rounding boundary."""
+    gam = n_terms * U32 / (1 - n_terms * U32)
+    tol = gam * a
+    lo, hi = y - tol, y + tol
+    if relu:
+        lo, hi, y = torch.relu(lo), torch.relu(hi), torch.relu(y)
+    rl, rh = _bf16(lo.permute(0, 2, 3, 1)), _bf16(hi.permute(0, 2, 3, 1))
+    g = g_bits[..., :y.shape[1]]
+    gv, lv, hv = (ref.bf16_bits_to_f32(t) for t in (g, rl, rh))
+    ok = (gv >= lv) & (gv <= hv)
+    assert ok.all(), (what, np.argwhere(~ok)[:5])
+    # most values sit far from a boundary: there the roundings agree and the
+    # GPU value must be that rounding exactly (random weights cancel often,
+    # so a few per cent of the intervals hold a boundary)
+    exact = rl == rh
+    assert (g[exact] == rl[exact]).all(), what
+    assert exact.mean() > 0.9, (what, exact.mean())
 
 
 # sizes: ragged row blocks and column tiles of every dilation; H = 200 gives
 # seven row blocks per lattice at dilation 1; 16 x 16 (the smallest frame) is
-# narrower than a tile and shorter than the largest dilation
+# narrower than a tile and shorter than the largest dilation; 1242 x 375 is
+# the benchmark's frame, one at a time (8-row lattice walks) and sixteen per
+# call (32-row walks, the learned check of a batch)
 @pytest.mark.parametrize("F,H,W", [(1, 37, 70), (2, 64, 129), (1, 200, 300), (1, 16, 16),
-                                   (3, 16, 17)])
+                                   (3, 16, 17), (1, 375, 1242), (16, 375, 1242)])
 def test_forward_matches_reference(F, H, W):
-    """Activations within one bf16 rounding step, logits within a tolerance
-    derived from fp32 accumulation of bf16 products."""
+    """Layer by layer on the GPU's own inputs: each bf16 activation is the
+    rounding of the fp32 reference value within the accumulation error
+    bound, and the logits are within that bound element by element.  End to
+    end (the reference's own activations): the learned mask differs only
+    where the reference logit is within one bf16 step of the last layer's
+    terms of zero."""
+    print(f"case forward F={F} {H}x{W}", flush=True)
     _, wbits, b = _params_bits(1)
     x0 = _random_x0(F, H, W, 3)
     z, acts = sldf.surrogate_forward(torch.from_numpy(x0.view(np.int16)).cuda(),
                                      torch.from_numpy(wbits.view(np.int16)).cuda(),
                                      torch.from_numpy(b).cuda())
     torch.cuda.synchronize()
-    zr, ar, _ = ref.forward(x0, wbits, b)
-    zr = zr.numpy()
-    for l in range(3):
-        g = ref.bf16_bits_to_f32(acts[l].cpu().numpy().view(np.uint16))
-        r = ar[l].permute(0, 2, 3, 1).numpy()
-        # rounding boundaries may differ by one bf16 step (2^-8 relative)
-        assert np.abs(g - r).max() <= 2 ** -7 * max(1.0, np.abs(r).max()), l
-        assert (np.abs(g - r) <= 2 ** -7 * np.maximum(np.abs(r), 1e-2)).mean() > 0.999, l
-    zg = z.cpu().numpy()
-    scale = np.abs(zr).max()
-    assert np.abs(zg - zr).max() <= 2e-2 * scale
-    assert np.abs(zg - zr).mean() <= 1e-3 * scale
+    params = ref.unpack(ref.bf16_bits_to_f32(wbits), b)
+    g_acts = [a.cpu().numpy().view(np.uint16) for a in acts]
+    inputs = [_nchw(x0)] + [_nchw(g) for g in g_acts]
+    with torch.no_grad():
+        for l in range(3):
+            w, bb, dil = params[l]
+            y, a = _layer(inputs[l], w, bb, dil)
+            _check_layer_output(g_acts[l], y, a, 9 * w.shape[1] + 1, True, f"layer {l + 1}")
+        w, bb, dil = params[3]
+        y, a = _layer(inputs[3], w, bb, dil)
+        n = 9 * w.shape[1] + 1
+        tol = (n * U32 / (1 - n * U32)) * a[:, 0]
+        zg = z.cpu()
+        assert ((zg - y[:, 0]).abs() <= tol).all(), "logits"
+        # end to end: rounding boundaries taken differently upstream move a
+        # logit by about one bf16 step of the last layer's terms at most
+        ze, _, _ = ref.forward(x0, wbits, b)
+        flip = (zg > 0) != (ze > 0)
+        tau = 2.0 ** -7 * a[:, 0]
+        assert (ze[flip].abs() <= tau[flip]).all(), "mask flips away from zero"
+        assert ((zg - ze).abs() <= tau).float().mean() > 0.999
+
+
+def _rne_interval(v, delta):
+    """bf16 rounding of every value in [v - delta, v + delta]: the rounding
+    of v, and how far the roundings of the interval ends are from it."""
+    mid = ref.round_bf16(v)
+    lo, hi = ref.round_bf16(v - delta), ref.round_bf16(v + delta)
+    return mid, torch.maximum((hi - mid).abs(), (mid - lo).abs())
 
 
 def test_backward_matches_reference():
-    """Gradients of the masked BCE loss against autograd on the CPU."""
+    """Gradients of the masked BCE loss, element by element, against an fp32
+    CPU backward pass on the GPU's own forward activations (both sides take
+    the same ReLU masks) that stores the logit gradient and each hidden
+    gradient map as bf16 (round to nearest even), as the kernels do.
+
+    The two sides then differ only in fp32 summation order, and where a
+    stored map value lies so close to a bf16 rounding boundary that the two
+    orders round it to neighbouring values.  The test carries that through
+    by interval arithmetic: at each map, the GPU value is a rounding of some
+    value within gamma_n sum|terms| (n terms, gamma_n = n u / (1 - n u),
+    u = 2^-24) plus the propagated bound of the input map's differences,
+    and its difference from the reference's rounding is bounded by the
+    roundings of the interval ends.  Each weight and bias gradient is then
+    within gamma_N sum|terms| of its N = F H W terms plus the propagated
+    bound of its gradient map.  A wrong tap, channel, transposition or gate
+    in dgrad or wgrad is off by the order of the gradient itself; dgrad is
+    covered through the weight gradients of the layers below it."""
     F, H, W = 2, 48, 96
     master, wbits, b = _params_bits(2)
     x0 = _random_x0(F, H, W, 5)
@@ -83,30 +169,56 @@ def test_backward_matches_reference():
     tc = 2
     trainer = sldf.SurrogateTrainer(W, H, F, torch.from_numpy(master))
     g = torch.zeros(ref.N_W + ref.N_B, dtype=torch.float32, device="cuda")
-    trainer.step(torch.from_numpy(x0.view(np.int16)).cuda(), torch.from_numpy(labels).cuda(),
-                 torch.from_numpy(rho.view(np.int16)).cuda(), tc, update=False, grads_out=g)
+    x0_d = torch.from_numpy(x0.view(np.int16)).cuda()
+    trainer.step(x0_d, torch.from_numpy(labels).cuda(), torch.from_numpy(rho.view(np.int16)).cuda(),
+                 tc, update=False, grads_out=g)
+    zg, acts = sldf.surrogate_forward(x0_d, torch.from_numpy(wbits.view(np.int16)).cuda(),
+                                      torch.from_numpy(b).cuda())
     torch.cuda.synchronize()
     g = g.cpu().numpy()
-    # reference loss: mean over all pixels of the masked BCE
-    z, _, params = ref.forward(x0, wbits, b, straight_through=True)
+    params = ref.unpack(ref.bf16_bits_to_f32(wbits), b)
+    ins = [_nchw(x0)] + [_nchw(a.cpu().numpy().view(np.uint16)) for a in acts]
     m = torch.from_numpy((rho > tc).astype(np.float32))
     y = torch.from_numpy(labels.astype(np.float32))
-    loss = (m * (torch.nn.functional.softplus(z) - y * z)).sum() / (F * H * W)
-    loss.backward()
+    gam = lambda n: n * U32 / (1 - n * U32)
+    # logit gradient m (sigma(z) - y) / (F H W); the GPU's sigmoid (fast exp
+    # and division) is taken as good to 2^-16 relative, far below a bf16 step
+    sg = torch.sigmoid(zg.cpu())
+    inv_n = 1.0 / (F * H * W)
+    gcur, err = _rne_interval((m * (sg - y) * inv_n)[:, None], (m * sg * 2.0 ** -16 * inv_n)[:, None])
+    gout, eout = [None] * 4, [None] * 4
+    for li in (3, 2, 1, 0):
+        w, _, dil = params[li]
+        gout[li], eout[li] = gcur, err
+        if li > 0:
+            mask = (ins[li] > 0).float()
+            back = lambda t, ww: torch.nn.grad.conv2d_input(ins[li].shape, ww, t, padding=dil,
+                                                            dilation=dil) * mask
+            v = back(gcur, w)
+            delta = gam(9 * w.shape[0]) * back(gcur.abs(), w.abs()) + back(err, w.abs())
+            gcur, err = _rne_interval(v, delta)
+    N = F * H * W
     off, boff = 0, 0
-    for li, ((oc, ic, _), cout) in enumerate(zip(ref.LAYERS, ref.COUT)):
+    for li, ((oc, ic, dil), cout) in enumerate(zip(ref.LAYERS, ref.COUT)):
+        w = params[li][0]
+        wg = lambda a, t: torch.nn.grad.conv2d_weight(a, w.shape, t, padding=dil,
+                                                      dilation=dil).numpy()
+        rw = wg(ins[li], gout[li])
+        bound = gam(N) * wg(ins[li].abs(), gout[li].abs()) + wg(ins[li].abs(), eout[li])
         gw = g[off:off + 9 * oc * ic].reshape(3, 3, oc, ic).transpose(2, 3, 0, 1)[:cout]
-        rw = params[li][0].grad.numpy()
-        err = np.linalg.norm(gw - rw) / np.linalg.norm(rw)
-        assert err < 2e-2, (li, err)
+        bad = np.abs(gw - rw) > bound + 1e-12
+        assert not bad.any(), (li, np.argwhere(bad)[:5], np.abs(gw - rw).max())
+        # the bound is not vacuous: it is a small fraction of the gradient
+        assert bound.sum() < 0.25 * np.abs(rw).sum(), (li, bound.sum() / np.abs(rw).sum())
         gb = g[ref.N_W + boff:ref.N_W + boff + cout]
-        rb = params[li][1].grad.numpy()
-        assert np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-12) < 2e-2, li
+        rb = gout[li].sum(dim=(0, 2, 3)).numpy()
+        bb = (gam(N) * gout[li].abs() + eout[li]).sum(dim=(0, 2, 3)).numpy()
+        assert (np.abs(gb - rb) <= bb + 1e-12).all(), li
         # padding entries carry no gradient
         pad = g[off:off + 9 * oc * ic].reshape(9, oc, ic)
         assert (pad[:, cout:, :] == 0).all()
         if li == 0:
-            assert (pad[:, :, 5:] == 0).all()
+            assert (pad[:, :, ref.N_IN:] == 0).all()
         off += 9 * oc * ic
         boff += cout
 
@@ -129,7 +241,11 @@ def test_train_step_deterministic_and_descends():
     for _ in range(30):
         st = t.step(x0, labels, rho, 2)
         losses.append(float(st[0].cpu()))
-    assert losses[-1] < 0.8 * losses[0], losses
+    # the labels are random: below the entropy of their frequency (the best
+    # constant predictor) only by fitting the inputs pixel by pixel
+    p1 = float(labels.float().mean())
+    entropy = -(p1 * np.log(p1) + (1 - p1) * np.log(1 - p1))
+    assert losses[-1] < 0.9 * losses[0] and losses[-1] < entropy, (losses, entropy)
 
 
 # both path pass schedules (1 paired, 2 split), 4 and 8 paths
@@ -191,3 +307,27 @@ def test_learned_requires_weights():
     with pytest.raises(sldf.SldfError) as ei:
         ctx.run(img, img, lid)
     assert ei.value.status == sldf.ESTATE
+
+
+def test_committed_weights_agree_with_plain_check_on_heldout_frames():
+    """The committed learned-check weights on held-out frames of the
+    surrogate workload (paper-scale synthetic frames 2000..2007, never seen
+    in training): the learned sldf_run_batch with its default fallback
+    setting agrees with the plain check (Eq. 6) on at least 99 % of pixels."""
+    from paper_2504_05148_amd.train_surrogate import load_weights
+    w, b, meta = load_weights()
+    frames = [synth.make_frame(synth.KITTI, synth.CONFIG_IDS["surrogate"], 2000 + i)
+              for i in range(8)]
+    F, D = len(frames), 128
+    left = sldf.device_images(np.stack([f["left"] for f in frames]))
+    right = sldf.device_images(np.stack([f["right"] for f in frames]))
+    lid = torch.stack([sldf.quantize_lidar(torch.from_numpy(f["lidar"]).cuda(), D)
+                       for f in frames])
+    _, vp = sldf.Context(sldf.default_params(batch=F)).run_batch(left, right, lid)
+    cl = sldf.Context(sldf.default_params(batch=F, check_impl=1))
+    cl.set_surrogate(w, b)
+    _, vl = cl.run_batch(left, right, lid)
+    torch.cuda.synchronize()
+    agree = float((vl == vp).float().mean())
+    print(f"held-out agreement {agree:.5f}", flush=True)
+    assert agree >= 0.99

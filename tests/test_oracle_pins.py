@@ -524,7 +524,8 @@ def test_surrogate_features_worked_example():
     f = oracle.surrogate_features(S, dstar, rho, 8, 1200)
     sS = np.float32(1) / np.float32(8 * 1200)
     exp = [np.float32(100) * sS, np.float32(104) * sS, np.float32(2) * sS,
-           np.float32(5) * (np.float32(1) / np.float32(D)), np.float32(7) / np.float32(32)]
+           np.float32(5) * (np.float32(1) / np.float32(D)), np.float32(7) / np.float32(32),
+           1.0]    # pixel x = 0 with d* = 5 has no matching pixel: margin 16 / 16
     assert f[0, 0].tolist() == [float(v) for v in exp]
     # range ends: no curvature; residual clipped at 32
     dstar = np.array([[0]], np.int32)
@@ -533,9 +534,101 @@ def test_surrogate_features_worked_example():
     assert f[0, 0, 1] == np.float32(min((d - 5) ** 2 + 100 for d in range(2, D))) * sS
 
 
+def _occlusion_brute(dstar):
+    """The occlusion margin written out per pixel with Python loops."""
+    H, W = dstar.shape
+    out = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            q = x - int(dstar[y, x])
+            right = [x2 - int(dstar[y, x2]) for x2 in range(x + 1, W)]
+            if q < 0:
+                v = 16
+            elif not right:
+                v = -16
+            else:
+                v = max(-16, min(16, q - min(right)))
+            out[y, x] = v / 16
+    return out
+
+
+def test_occlusion_margin_worked_example_and_brute_force():
+    """Sixth surrogate input: d* = [0, 0, 3, 0, 0] matches the right-image
+    pixels q = [0, 1, -1, 3, 4]: pixel 2 has no match (16); pixels 0 and 1
+    are overtaken by pixel 2's match q = -1 (margins 1 and 2); pixel 3 is
+    visible (q = 3 < 4: -1); the last pixel has nothing to its right (-16)."""
+    dstar = np.array([[0, 0, 3, 0, 0]], np.int32)
+    S = np.zeros((1, 5, 8), np.int32)
+    rho = np.zeros((1, 5), np.uint16)
+    f = oracle.surrogate_features(S, dstar, rho, 8, 1200)[..., 5]
+    assert (f[0] * 16).tolist() == [1.0, 2.0, 16.0, -1.0, -16.0]
+    # a fronto-parallel row: every pixel visible by exactly one pixel, except
+    # the first c pixels (no match) and the last one
+    c = 3
+    f = oracle.surrogate_features(np.zeros((1, 12, 8), np.int32),
+                                  np.full((1, 12), c, np.int32), np.zeros((1, 12), np.uint16),
+                                  8, 1200)[..., 5]
+    assert (f[0] * 16).tolist() == [16.0] * c + [-1.0] * (12 - c - 1) + [-16.0]
+    rng = np.random.default_rng(11)
+    for W in (1, 2, 7, 40):
+        dstar = rng.integers(0, 24, size=(3, W)).astype(np.int32)
+        f = oracle.surrogate_features(np.zeros((3, W, 24), np.int32), dstar,
+                                      np.zeros((3, W), np.uint16), 8, 1200)[..., 5]
+        assert (f == _occlusion_brute(dstar)).all(), W
+
+
 def test_bf16_rounding():
     x = np.array([1.0, 1.00390625, 1.005859375, -2.5, 3.0e-5], np.float32)
     b = oracle.bf16_round(x)
     # 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1.0); 1 + 1.5 * 2^-8
     # rounds up to 1 + 2^-7
     assert oracle.bf16_to_f32(b).tolist()[:4] == [1.0, 1.0, 1.0078125, -2.5]
+
+
+def test_full_census_worked_examples():
+    """Full census (census_kind 1), 5 x 5: every offset but the centre in
+    raster order, bit k = [I(p + o_k) < I(p)], LSB first.  Horizontal ramp
+    I = x: the bits of the offsets with dx < 0, i.e. the first two of each
+    window row (bits 0, 1 | 5, 6 | 10, 11 | 14, 15 | 19, 20: the centre row
+    has four offsets).  Vertical ramp I = y: the two rows above, bits 0..9.
+    Decreasing ramp I = -x: dx > 0, bits 3, 4 | 8, 9 | 12, 13 | 17, 18 |
+    22, 23.  Constant image: 0.  Border pixels: 0."""
+    H, W = 9, 12
+    ramp_x = np.tile(np.arange(W, dtype=np.uint8) * 7, (H, 1))
+    ramp_y = np.tile((np.arange(H, dtype=np.uint8) * 9)[:, None], (1, W))
+    ramp_nx = np.tile((200 - np.arange(W) * 7).astype(np.uint8), (H, 1))
+    bits = lambda ks: sum(1 << k for k in ks)
+    cases = [(ramp_x, bits([0, 1, 5, 6, 10, 11, 14, 15, 19, 20])),
+             (ramp_y, bits(range(10))),
+             (ramp_nx, bits([3, 4, 8, 9, 12, 13, 17, 18, 22, 23])),
+             (np.full((H, W), 77, np.uint8), 0)]
+    for img, code in cases:
+        c = oracle.census(img, 5, 5, kind=1)
+        assert (c[2:H - 2, 2:W - 2] == code).all()
+        inner = np.zeros((H, W), bool)
+        inner[2:H - 2, 2:W - 2] = True
+        assert (c[~inner] == 0).all()
+    assert oracle.census_bits(5, 5, 1) == 24 and oracle.census_bits(9, 7, 1) == 62
+
+
+def test_full_census_brute_force():
+    """Against a numpy brute force written from the definition."""
+    rng = np.random.default_rng(21)
+    img = rng.integers(0, 256, size=(14, 19)).astype(np.uint8)
+    for cw, ch in ((3, 3), (5, 5), (3, 9), (7, 3)):
+        c = oracle.census(img, cw, ch, kind=1)
+        rx, ry = cw // 2, ch // 2
+        H, W = img.shape
+        for y in range(H):
+            for x in range(W):
+                exp = 0
+                if rx <= x < W - rx and ry <= y < H - ry:
+                    k = 0
+                    for dy in range(-ry, ry + 1):
+                        for dx in range(-rx, rx + 1):
+                            if dx == 0 and dy == 0:
+                                continue
+                            if img[y + dy, x + dx] < img[y, x]:
+                                exp |= 1 << k
+                            k += 1
+                assert c[y, x] == exp, (cw, ch, y, x)
