@@ -74,6 +74,34 @@ SGM_SOURCES = ("k_sgm_sweep.hip", "sgm_common.h", "sldf_internal.h")
 SWEEP_MIN_FRAMES = 16
 
 
+VALU_OPS = ("v_pk_add_u16", "v_pk_min_u16", "v_pk_minimum3_f16", "v_add3_u32", "v_alignbit_b32",
+            "v_bcnt_u32_b32", "v_xor_b32", "v_min_u32_dpp")
+VALU_PACKED = 3          # the first three are packed 2 x 16-bit
+
+
+def valu_peak(iters: int = 8000):
+    """Sustained rates of the SGM kernels' integer instructions on this
+    device (lane instructions/s), from the throughput probe library, and the
+    peaks the roofline takes: min(published, measured) per class, the packed
+    class at two 16-bit ops per instruction."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2504_05148_amd", "libvalu_peak.so"))
+    lib.valu_peak_measure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+    rates = {}
+    for i, name in enumerate(VALU_OPS):
+        r, ms = ctypes.c_double(), ctypes.c_double()
+        rc = lib.valu_peak_measure(i, iters, ctypes.byref(r), ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"valu_peak_measure({name}) failed: {rc}")
+        rates[name] = r.value
+    packed = min(rates[n] for n in VALU_OPS[:VALU_PACKED])
+    int32 = min(rates[n] for n in VALU_OPS[VALU_PACKED:])
+    return dict(rates_tinst_s={k: round(v / 1e12, 2) for k, v in rates.items()},
+                peak16=min(PEAK_OPS16, 2 * packed), peak32=min(PEAK_OPS32, int32),
+                measured16=2 * packed, measured32=int32)
+
+
 def sgm_traffic(frames: int):
     """HBM bytes per SGM launch from the committed counter summary, if it
     was taken on the current kernel source and the same launch size."""
@@ -303,7 +331,9 @@ def main():
     launches_per_step = max(sgm_launches, 1) / K
     s16, s32 = sgm_ops_per_step(B, 2)
     ops16, ops32 = s16 / launches_per_step, s32 / launches_per_step   # per launch, averaged
-    floor_s = ops16 / PEAK_OPS16 + ops32 / PEAK_OPS32
+    vp = valu_peak()
+    pk16, pk32 = vp["peak16"], vp["peak32"]
+    floor_s = ops16 / pk16 + ops32 / pk32
     peak = (ops16 + ops32) / floor_s
     achieved = (ops16 + ops32) / avg_launch_s
     traffic = sgm_traffic(B)
@@ -314,14 +344,20 @@ def main():
                     measured_in=f"one-stream run, {B} frames per call",
                     ops_per_launch=int(ops16 + ops32),
                     peak_basis="u16 recurrence at the packed-16 peak, the rest at the "
-                               "32-bit peak",
-                    frac_int32=round(achieved / PEAK_OPS32, 4))
+                               "32-bit peak; each peak the smaller of the published figure "
+                               "and the probe's sustained rate",
+                    peak_published=round((ops16 + ops32) / (ops16 / PEAK_OPS16 + ops32 / PEAK_OPS32)
+                                         / 1e12, 3),
+                    valu_probe=dict(rates_tinst_s=vp["rates_tinst_s"],
+                                    measured16_tops=round(vp["measured16"] / 1e12, 2),
+                                    measured32_tops=round(vp["measured32"] / 1e12, 2)),
+                    frac_int32=round(achieved / pk32, 4))
     if traffic:
         bw = traffic / avg_launch_s
         roofline.update(hbm_tb_s=round(bw / 1e12, 3), hbm_frac=round(bw / HBM_PEAK, 4))
     p16, p32 = pipeline_ops_per_frame()
-    floor_cw = p16 / PEAK_OPS16 + p32 / PEAK_OPS32
-    floor_32 = (p16 + p32) / PEAK_OPS32
+    floor_cw = p16 / pk16 + p32 / pk32
+    floor_32 = (p16 + p32) / pk32
     pipeline = dict(ops_per_frame=int(p16 + p32),
                     floor_fps_class_weighted=round(1 / floor_cw, 1),
                     floor_fps_int32=round(1 / floor_32, 1),

@@ -10,6 +10,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsldf.so")
+# the vector-ALU throughput probe (measurement support), a library of its own
+PROBE_SRC = os.path.join(HERE, "probe", "valu_peak.hip")
+PROBE_LIB = os.path.join(HERE, "libvalu_peak.so")
 OBJ = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -33,8 +36,10 @@ def build(verbose: bool = False) -> str:
             print(" ".join(cmd), file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(srcs) + 1)) as ex:
+        probe = ex.submit(build_probe)
         objs = list(ex.map(compile_one, srcs))
+        probe.result()
     tmp = LIB + ".tmp"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)
@@ -42,6 +47,16 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_probe() -> str:
+    tmp = PROBE_LIB + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, "-shared", PROBE_SRC, "-o", tmp], capture_output=True,
+                       text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

@@ -72,8 +72,8 @@ struct SweepLds {
 // pass-coordinate position u of row j at step t
 __device__ __forceinline__ int sw_pos(int t, int j) { return t - 2 * j; }
 
-template <int G, int PASS, int NP, int VIEW>
-__device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP>& sm, int j,
+template <int G, int PASS, int NP, int VIEW, int NW>
+__device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, NW>& sm, int j,
                                               int g, int frame, int band, int rpb, int T,
                                               uint32_t* sbuf)
 {
@@ -172,13 +172,18 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP>&
                     rec_lane<G, NR>(Ldr, mdr, C, p1x2, p2x2, gfirst, glast, edge);
                     rec_lane<G, NR>(Ldl, mdl, C, p1x2, p2x2, gfirst, glast, edge);
                 }
-                // the set's share of S (Eq. 3)
+                // the set's share of S (Eq. 3); every partial sum of paths fits
+                // its u16 half (the host bounds |R| (C' + P2) below 2^16), so
+                // 32-bit adds of the packed words are exact
                 uint32_t St[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    St[q] = pk_add(Lh[q], Ldn[q]);
-                    if (NP == 8) St[q] = pk_add(St[q], pk_add(Ldl[q], Ldr[q]));
-                    if (kLast) St[q] = pk_add(St[q], sa[q]);
+                    if (NP == 8) {
+                        St[q] = add3(Lh[q], Ldn[q], Ldl[q]);
+                        St[q] = kLast ? add3(St[q], Ldr[q], sa[q]) : St[q] + Ldr[q];
+                    } else {
+                        St[q] = kLast ? add3(Lh[q], Ldn[q], sa[q]) : Lh[q] + Ldn[q];
+                    }
                 }
                 // cost of the next step (its inputs were loaded a step ago)
                 cost(inext, u + 1, C);
@@ -243,11 +248,11 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP>&
 
 // The loader wave: hands the band's last row to the band below (producer)
 // and the band above's last row to this band's first row (consumer).
-template <int G, int NP>
-__device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP>& sm, int lane,
+template <int G, int NP, int NW>
+__device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, NW>& sm, int lane,
                                              int fv, int band, int nbands, int rpb, int T)
 {
-    constexpr int NX = SweepLds<G, NP>::NX;
+    constexpr int NX = SweepLds<G, NP, NW>::NX;
     constexpr int NCH = NX * G + 1;              // chunks per pixel in use
     constexpr int CPL = (NCH + 63) / 64;         // chunks per loader lane
     constexpr int kRing = kSwAhead;
@@ -360,12 +365,12 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP>& 
     }
 }
 
-template <int G, int PASS, int NP>
-__global__ __launch_bounds__(kSwWaves * 64, 4) void sgm_sweep_kernel(SgmArgs a)
+template <int G, int PASS, int NP, int NW>
+__global__ __launch_bounds__(NW * 64, 4) void sgm_sweep_kernel(SgmArgs a)
 {
-    constexpr int ROWS = sweep_rows<G>();
+    constexpr int ROWS = sweep_rows<G, NW>();
     constexpr int D = G * 8;
-    __shared__ SweepLds<G, NP> sm;
+    __shared__ SweepLds<G, NP, NW> sm;
     __shared__ u32x4 sbuf[PASS == 1 ? ROWS * G : 1];
     const int tid = threadIdx.x;
     if (tid == 0)
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(kSwWaves * 64, 4) void sgm_sweep_kernel(SgmArgs a)
     {
         uint32_t* z = reinterpret_cast<uint32_t*>(&sm.xch[0][0][0][0]);
         constexpr int nz = (int)(sizeof(sm.xch) + sizeof(sm.xm)) / 4;
-        for (int i = tid; i < nz; i += kSwWaves * 64) z[i] = 0u;
+        for (int i = tid; i < nz; i += NW * 64) z[i] = 0u;
     }
     build_pattern<D>(a, sm.pat);
     __syncthreads();
@@ -389,15 +394,15 @@ __global__ __launch_bounds__(kSwWaves * 64, 4) void sgm_sweep_kernel(SgmArgs a)
         // handed on by the loader one step later; a whole number of both unrolls
         const int T = -2 + (a.W + 2 * (rpb - 1) + 3 + kSwAhead - 1) / kSwAhead * kSwAhead;
         const int wave = tid >> 6;
-        if (wave == kSwWaves - 1) {
-            sweep_loader<G, NP>(a, sm, tid & 63, fv, band, a.blocks_per_fv, rpb, T);
+        if (wave == NW - 1) {
+            sweep_loader<G, NP, NW>(a, sm, tid & 63, fv, band, a.blocks_per_fv, rpb, T);
         } else {
             const int j = tid / G, g = tid % G;
             uint32_t* sb = reinterpret_cast<uint32_t*>(sbuf);
             if (view == 0)
-                sweep_compute<G, PASS, NP, 0>(a, sm, j, g, frame, band, rpb, T, sb);
+                sweep_compute<G, PASS, NP, 0, NW>(a, sm, j, g, frame, band, rpb, T, sb);
             else
-                sweep_compute<G, PASS, NP, 1>(a, sm, j, g, frame, band, rpb, T, sb);
+                sweep_compute<G, PASS, NP, 1, NW>(a, sm, j, g, frame, band, rpb, T, sb);
         }
     }
     // the last workgroup to finish resets the ticket counters for the next launch
@@ -412,24 +417,38 @@ __global__ __launch_bounds__(kSwWaves * 64, 4) void sgm_sweep_kernel(SgmArgs a)
     }
 }
 
-template <int G, int NP>
+template <int G, int NP, int NW>
 static hipError_t launch_sweep_g(const SgmArgs& a, int pass, dim3 grid, hipStream_t s)
 {
     if (pass == 0)
-        hipLaunchKernelGGL((sgm_sweep_kernel<G, 0, NP>), grid, dim3(kSwWaves * 64), 0, s, a);
+        hipLaunchKernelGGL((sgm_sweep_kernel<G, 0, NP, NW>), grid, dim3(NW * 64), 0, s, a);
     else
-        hipLaunchKernelGGL((sgm_sweep_kernel<G, 1, NP>), grid, dim3(kSwWaves * 64), 0, s, a);
+        hipLaunchKernelGGL((sgm_sweep_kernel<G, 1, NP, NW>), grid, dim3(NW * 64), 0, s, a);
     return hipGetLastError();
 }
 
-int sweep_rows_host(int D)
+static int rows_of(int D, int nw)
 {
-    return D == 64 ? sweep_rows<8>() : D == 128 ? sweep_rows<16>() : sweep_rows<32>();
+    return (nw - 1) * (64 / (D / 8));
 }
-int sweep_bands(int H, int D) { return (H + sweep_rows_host(D) - 1) / sweep_rows_host(D); }
+
+// Workgroup size and bands of a launch: 16-wave workgroups (15 waves of rows,
+// one per compute unit: they fill its LDS), the rows spread evenly over the
+// fewest bands.  (Two 8-wave workgroups per unit, whose barriers do not run
+// in step, measured no faster.)
+SweepPlan sweep_plan(int W, int H, int D, int64_t n_fv)
+{
+    (void)W;
+    (void)n_fv;
+    const int rpw = 64 / (D / 8);
+    const int bands = (H + rows_of(D, kSwWaves) - 1) / rows_of(D, kSwWaves);
+    const int per = (H + bands - 1) / bands;
+    return SweepPlan{kSwWaves, bands, (per + rpw - 1) / rpw * rpw};
+}
+
 int64_t sweep_hand_bytes_per_fv(int W, int H, int D)
 {
-    const int nb = sweep_bands(H, D);
+    const int nb = sweep_plan(W, H, D, 1).bands;
     const int G = D / 8;
     return (int64_t)(nb - 1) * W * (3 * G + 1) * 16;
 }
@@ -440,16 +459,19 @@ hipError_t launch_sgm_sweep(const SgmArgs& a0, int D, int pass, int nviews, int 
     SgmArgs a = a0;
     a.nviews = nviews;
     a.n_fv = nviews * nframes;
-    a.blocks_per_fv = sweep_bands(a.H, D);       // bands per frame-view
-    // rows per band: H spread evenly over the bands, rounded up to whole waves
-    const int rpw = 64 / (D / 8);
-    const int per = (a.H + a.blocks_per_fv - 1) / a.blocks_per_fv;
-    a.rows_per_band = (per + rpw - 1) / rpw * rpw;
+    const SweepPlan pl = sweep_plan(a.W, a.H, D, a.n_fv);
+    a.blocks_per_fv = pl.bands;                  // bands per frame-view
+    a.rows_per_band = pl.rows_per_band;
     const int np = a.npaths;                     // 4 or 8
     dim3 grid((unsigned)(a.n_fv * a.blocks_per_fv));
-    if (D == 64) return np == 8 ? launch_sweep_g<8, 8>(a, pass, grid, s) : launch_sweep_g<8, 4>(a, pass, grid, s);
-    if (D == 128) return np == 8 ? launch_sweep_g<16, 8>(a, pass, grid, s) : launch_sweep_g<16, 4>(a, pass, grid, s);
-    return np == 8 ? launch_sweep_g<32, 8>(a, pass, grid, s) : launch_sweep_g<32, 4>(a, pass, grid, s);
+    if (D == 64)
+        return np == 8 ? launch_sweep_g<8, 8, kSwWaves>(a, pass, grid, s)
+                       : launch_sweep_g<8, 4, kSwWaves>(a, pass, grid, s);
+    if (D == 128)
+        return np == 8 ? launch_sweep_g<16, 8, kSwWaves>(a, pass, grid, s)
+                       : launch_sweep_g<16, 4, kSwWaves>(a, pass, grid, s);
+    return np == 8 ? launch_sweep_g<32, 8, kSwWaves>(a, pass, grid, s)
+                   : launch_sweep_g<32, 4, kSwWaves>(a, pass, grid, s);
 }
 
 }  // namespace sldf

@@ -41,6 +41,14 @@ __device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
     return u1(__builtin_elementwise_min(v2(a), v2(b)));
 }
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) { return u1(v2(a) + v2(b)); }
+// a + b + c as one instruction (the compiler would otherwise split it into a
+// subtract it can start early and an add)
+__device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 __device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) { return u1(v2(a) - v2(b)); }
 // Three-way packed minimum of u16 values below 0x7c00: such bit patterns
 // are positive finite fp16 numbers (denormals included, which the kernels
@@ -71,6 +79,7 @@ constexpr int kRowShr1 = 0x111;        // lane i <- lane i-1 within a row of 16
 constexpr int kRowShl1 = 0x101;        // lane i <- lane i+1 within a row of 16
 
 constexpr int kXcds = 8;               // MI355X: 8 XCDs, one L2 each
+constexpr int kCus = 256;              // compute units
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
@@ -341,11 +350,15 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
     for (int i = 1; i < NR; ++i) Dm[i] = __builtin_amdgcn_alignbit(L[i], L[i - 1], 16);
     Dm[NR] = __builtin_amdgcn_alignbit(nx, L[NR - 1], 16);
     const uint32_t mp2 = pk_add(m, p2x2);
+    // best + C - m in one 32-bit three-way add: in each half best >= m (every
+    // term of the minimum is at least m) and the result lies in [0, 0xffff],
+    // so the 32-bit sum of best, C and -(m, m) equals the packed one
+    const uint32_t negm = 0u - m;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
         uint32_t best = pk_min3(L[i], nb, mp2);
-        L[i] = pk_add(best, pk_sub(C[i], m));
+        L[i] = add3(best, C[i], negm);
     }
     m = group_min<G>(lane_min<NR>(L));
 }
