@@ -54,6 +54,13 @@ template <int G, int NW = kSwWaves>
 __host__ __device__ constexpr int sweep_rows() { return (NW - 1) * (64 / G); }
 // 16-byte chunks of one handoff pixel: dl, dn, dr states of G lanes + the three minima
 template <int G> __host__ __device__ constexpr int sweep_chunks() { return 3 * G + 1; }
+// A pixel's record in the handoff buffer is dword-major, [4][RECP] with the
+// chunk count padded to a multiple of 64: the loader lanes' stores and loads
+// of dword e of their chunks then cover whole cache lines.
+template <int G> __host__ __device__ constexpr int sweep_rec_pad()
+{
+    return (sweep_chunks<G>() + 63) / 64 * 64;
+}
 
 enum { kDirDL = 0, kDirDN = 1, kDirDR = 2 };
 
@@ -72,10 +79,20 @@ struct SweepLds {
 // pass-coordinate position u of row j at step t
 __device__ __forceinline__ int sw_pos(int t, int j) { return t - 2 * j; }
 
+// The outputs of the last 2G pixels of a row in the second sweep (LDS),
+// written to global memory 2G at a time (whole lines instead of one scattered
+// 2- or 4-byte store per pixel)
+template <int G>
+struct SweepStage {
+    int16_t d[2 * G];
+    float v[2 * G];
+    uint32_t f[4 * G];
+};
+
 template <int G, int PASS, int NP, int VIEW, int NW>
 __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, NW>& sm, int j,
                                               int g, int frame, int band, int rpb, int T,
-                                              uint32_t* sbuf)
+                                              uint32_t* sbuf, SweepStage<G>* ostage)
 {
     constexpr int NR = 4, K = 8, D = G * K;
     constexpr int RPW = 64 / G;                 // rows per wave
@@ -194,13 +211,36 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                     } else {
                         if (a.store_sum) store_s<NR>(la, o, St);
                         const int x = x0 + u * dx;
-                        const uint32_t px = (uint32_t)(y * W + x);
                         // the row's S(p, .) in LDS: the owner of d* reads its neighbours
                         u32x4* srow = reinterpret_cast<u32x4*>(sbuf) + j * G;
                         srow[g] = pack_v<NR>(St);
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        wta_emit<G, VIEW, NR>(a, St, d0, (size_t)frame * a.px_stride + px,
-                                              reinterpret_cast<const uint16_t*>(srow));
+                        // the pixel's outputs wait in the row's stage (slot x mod 2G)
+                        // until the row has walked down to a multiple of 2G
+                        SweepStage<G>& rs = ostage[j];
+                        const int slot = x % (2 * G);
+                        const WtaStage ws{&rs.d[slot], &rs.v[slot], &rs.f[2 * slot]};
+                        wta_emit<G, VIEW, NR>(a, St, d0, 0, reinterpret_cast<const uint16_t*>(srow),
+                                              ws);
+                        if (slot == 0) {
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                            const size_t rowp = (size_t)frame * a.px_stride + (size_t)y * W;
+#pragma unroll
+                            for (int k = 0; k < 2; ++k) {
+                                const int i = g + k * G;
+                                if (x + i < W) {
+                                    const size_t p = rowp + x + i;
+                                    a.wta[VIEW][p] = rs.d[i];
+                                    if (VIEW == 0) {
+                                        a.dsub[p] = rs.v[i];
+                                        if (a.feat) {
+                                            a.feat[2 * p] = rs.f[2 * i];
+                                            a.feat[2 * p + 1] = rs.f[2 * i + 1];
+                                        }
+                                    }
+                                }
+                            }
+                        }
                     }
                 }
                 // outputs for the row below; a dl path leaving past the row end
@@ -257,13 +297,14 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, N
     constexpr int CPL = (NCH + 63) / 64;         // chunks per loader lane
     constexpr int kRing = kSwAhead;
     const int W = a.W;
-    const int64_t rec = sweep_chunks<G>();       // chunk stride of a pixel in the buffer
+    constexpr int RECP = sweep_rec_pad<G>();
+    constexpr int64_t rec = 4 * RECP;            // dwords per pixel in the buffer
     // buffer of the boundary below this band and of the one above it
     uint32_t* const out = band + 1 < nbands
-                              ? a.hand + (((int64_t)fv * (nbands - 1) + band) * W) * rec * 4
+                              ? a.hand + (((int64_t)fv * (nbands - 1) + band) * W) * rec
                               : nullptr;
     uint32_t* const in = band > 0
-                             ? a.hand + (((int64_t)fv * (nbands - 1) + band - 1) * W) * rec * 4
+                             ? a.hand + (((int64_t)fv * (nbands - 1) + band - 1) * W) * rec
                              : nullptr;
     // chunk c of a pixel: c < NX G is lane c % G of direction c / G, chunk
     // NX G the NX minima
@@ -274,10 +315,10 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, N
             const int c = lane + 64 * h;
             u32x4 v = {0u, 0u, 0u, 0u};
             if (in && c < NCH && col < W) {
-                uint32_t* p = in + ((int64_t)col * rec + c) * 4;
+                uint32_t* p = in + (int64_t)col * rec + c;
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    v[e] = __hip_atomic_load(p + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    v[e] = __hip_atomic_load(p + e * RECP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             ring[k][h] = v;
         }
@@ -305,10 +346,10 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, N
                     for (int it = 0; it < kSwSpinMax && __builtin_amdgcn_ballot_w64(!ok); ++it) {
                         __builtin_amdgcn_s_sleep(2);
                         if (!ok) {
-                            uint32_t* p = in + ((int64_t)col * rec + c) * 4;
+                            uint32_t* p = in + (int64_t)col * rec + c;
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
-                                v[e] = __hip_atomic_load(p + e, __ATOMIC_RELAXED,
+                                v[e] = __hip_atomic_load(p + e * RECP, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                             ok = (v[0] & v[1] & v[2] & v[3]) & kSwTag;
                         }
@@ -322,10 +363,11 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, N
                 }
                 if (need) {
                     // clear what was consumed: the buffer is zero between launches
-                    uint32_t* p = in + ((int64_t)col * rec + c) * 4;
+                    uint32_t* p = in + (int64_t)col * rec + c;
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        __hip_atomic_store(p + e, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(p + e * RECP, 0u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[e] &= ~kSwTag;
@@ -353,10 +395,10 @@ __device__ __forceinline__ void sweep_loader(const SgmArgs& a, SweepLds<G, NP, N
 #pragma unroll
                         for (int e = 0; e < NX; ++e) v[e] = sm.xm[(t - 1) & 1][e][rpb];
                     }
-                    uint32_t* p = out + ((int64_t)xp * rec + c) * 4;
+                    uint32_t* p = out + (int64_t)xp * rec + c;
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        __hip_atomic_store(p + e, v[e] | kSwTag, __ATOMIC_RELAXED,
+                        __hip_atomic_store(p + e * RECP, v[e] | kSwTag, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
@@ -372,6 +414,7 @@ __global__ __launch_bounds__(NW * 64, 4) void sgm_sweep_kernel(SgmArgs a)
     constexpr int D = G * 8;
     __shared__ SweepLds<G, NP, NW> sm;
     __shared__ u32x4 sbuf[PASS == 1 ? ROWS * G : 1];
+    __shared__ SweepStage<G> ostage[PASS == 1 ? ROWS : 1];
     const int tid = threadIdx.x;
     if (tid == 0)
         sm.ticket = __hip_atomic_fetch_add(a.sync, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -400,9 +443,9 @@ __global__ __launch_bounds__(NW * 64, 4) void sgm_sweep_kernel(SgmArgs a)
             const int j = tid / G, g = tid % G;
             uint32_t* sb = reinterpret_cast<uint32_t*>(sbuf);
             if (view == 0)
-                sweep_compute<G, PASS, NP, 0, NW>(a, sm, j, g, frame, band, rpb, T, sb);
+                sweep_compute<G, PASS, NP, 0, NW>(a, sm, j, g, frame, band, rpb, T, sb, ostage);
             else
-                sweep_compute<G, PASS, NP, 1, NW>(a, sm, j, g, frame, band, rpb, T, sb);
+                sweep_compute<G, PASS, NP, 1, NW>(a, sm, j, g, frame, band, rpb, T, sb, ostage);
         }
     }
     // the last workgroup to finish resets the ticket counters for the next launch
@@ -449,8 +492,8 @@ SweepPlan sweep_plan(int W, int H, int D, int64_t n_fv)
 int64_t sweep_hand_bytes_per_fv(int W, int H, int D)
 {
     const int nb = sweep_plan(W, H, D, 1).bands;
-    const int G = D / 8;
-    return (int64_t)(nb - 1) * W * (3 * G + 1) * 16;
+    const int recp = D == 64 ? sweep_rec_pad<8>() : D == 128 ? sweep_rec_pad<16>() : sweep_rec_pad<32>();
+    return (int64_t)(nb - 1) * W * recp * 16;
 }
 
 hipError_t launch_sgm_sweep(const SgmArgs& a0, int D, int pass, int nviews, int nframes,

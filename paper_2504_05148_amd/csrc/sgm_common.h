@@ -363,6 +363,16 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
     m = group_min<G>(lane_min<NR>(L));
 }
 
+// Where wta_emit puts the owner lane's outputs of a pixel: null d writes them
+// to global memory at px; otherwise to these LDS slots (d*, the subpixel
+// disparity and the two cost-feature words), which the caller writes out
+// later with other pixels of the row in whole cache lines.
+struct WtaStage {
+    int16_t* d = nullptr;
+    float* v = nullptr;
+    uint32_t* f = nullptr;
+};
+
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
 // of (S, d), ties -> smallest d) and the parabola fit through S(d*-1),
 // S(d*), S(d*+1); the owning lane writes d* (and for the left view the
@@ -371,7 +381,8 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
 // the call), from which the owner reads the two neighbours of d*.
 template <int G, int VIEW, int NR = 4>
 __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR], int d0,
-                                         size_t px, const uint16_t* simg = nullptr)
+                                         size_t px, const uint16_t* simg = nullptr,
+                                         const WtaStage& stage = WtaStage{})
 {
     constexpr int K = 2 * NR, D = G * K;
     uint32_t best = 0xffffffffu;
@@ -398,7 +409,8 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
         second = group_min<G>(second);
     }
     if (db >= d0 && db < d0 + K) {
-        a.wta[VIEW][px] = (int16_t)db;
+        if (stage.d) stage.d[0] = (int16_t)db;
+        else a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
             uint32_t A = 0, B = best >> 9, Cc = 0;   // S(d*) is the minimum itself
             if (simg) {
@@ -427,10 +439,18 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
             const int den = (int)A - 2 * (int)B + (int)Cc;
             if (a.subpixel && db > 0 && db < D - 1 && den > 0)
                 v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
-            a.dsub[px] = v;
-            if (a.feat) {
-                a.feat[2 * px] = B | (second << 16);
-                a.feat[2 * px + 1] = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+            const uint32_t f0 = B | (second << 16);
+            const uint32_t f1 = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+            if (stage.d) {
+                stage.v[0] = v;
+                stage.f[0] = f0;
+                stage.f[1] = f1;
+            } else {
+                a.dsub[px] = v;
+                if (a.feat) {
+                    a.feat[2 * px] = f0;
+                    a.feat[2 * px + 1] = f1;
+                }
             }
         }
     }
