@@ -96,7 +96,7 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
 {
     constexpr int NR = 4, K = 8, D = G * K;
     constexpr int RPW = 64 / G;                 // rows per wave
-    constexpr int kRing = 2;
+    constexpr int kRing = PASS == 0 ? 4 : 2;   // steps of loads in flight
     constexpr bool kLast = PASS == 1;
     const int yp = band * rpb + j;              // row in pass coordinates
     const bool live = j < rpb && yp < a.H;

@@ -583,6 +583,15 @@ def test_bf16_rounding():
     # 1 + 2^-8 is a tie between 1 and 1 + 2^-7 -> even (1.0); 1 + 1.5 * 2^-8
     # rounds up to 1 + 2^-7
     assert oracle.bf16_to_f32(b).tolist()[:4] == [1.0, 1.0, 1.0078125, -2.5]
+    # against PyTorch's float32 -> bfloat16 conversion (round to nearest even) on
+    # random values of every magnitude and on exact ties
+    import torch
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000)).astype(np.float32)
+    ties = ((rng.integers(0, 1 << 16, 2000).astype(np.uint32) << 16) | 0x8000).view(np.float32)
+    x = np.concatenate([x, ties[np.isfinite(ties)]])
+    ref_bits = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert (oracle.bf16_round(x) == ref_bits).all()
 
 
 def test_full_census_worked_examples():
