@@ -600,16 +600,18 @@ hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void fill_i32_kernel(int32_t* p, int n, int v)
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int v)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s)
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                       0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -578,7 +578,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
             // once (sweep B, the other four, WTA); the handoff buffer and the
             // launch words start at zero (then every launch leaves them so)
             if (!ctx->sweep_ready) {
-                if (launch_fill_i32((int32_t*)b.hand, (int)(b.hand_bytes / 4), 0, s) != hipSuccess ||
+                if (launch_fill_i32((int32_t*)b.hand, (int64_t)(b.hand_bytes / 4), 0, s) != hipSuccess ||
                     launch_fill_i32(b.sync, 4, 0, s) != hipSuccess)
                     return false;
                 ctx->sweep_ready = 1;

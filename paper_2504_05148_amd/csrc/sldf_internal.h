@@ -270,7 +270,7 @@ hipError_t launch_bce(const LossArgs& a, int nframes, hipStream_t s);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_sync_weights(const float* master, uint16_t* w_bf16, float* bias, hipStream_t s);
 hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s);
-hipError_t launch_fill_i32(int32_t* p, int n, int v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int v, hipStream_t s);
 
 // path pass roles: the first pass stores S, middle ones add into it, the
 // last takes the WTA; kMiddle2 also adds the second term S2 of a split pass
