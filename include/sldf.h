@@ -313,7 +313,7 @@ sldf_status sldf_timing_read(sldf_ctx* ctx, double* ms, int64_t* launches);
    the plain check of Eq. 6 stays the reference and the fallback) ----
    Network: 3x3 convolutions with dilations 1, 3, 9, 27 (an 81 x 81 receptive
    field covered without gaps); channels
-   5 (+3 zero) -> 32 -> 32 -> 32 -> 1; ReLU after the first three; bf16
+   6 (+2 zero) -> 32 -> 32 -> 32 -> 1; ReLU after the first three; bf16
    weights and activations, fp32 accumulation; logit > 0 means "consistent".
    Parameter blob (device, caller-owned, may be shared by contexts):
      weights: bf16 (uint16 bit patterns), sldf_surrogate_num_weights() of
@@ -328,6 +328,14 @@ int32_t sldf_surrogate_num_biases(void);
    kept, not copied; NULL detaches).  Errors: EINVAL. */
 sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
                                        const float* biases);
+
+/* The same from one device blob of sldf_surrogate_blob_bytes() bytes: the
+   bf16 weights, zero padding to a 256-byte boundary, then the float biases.
+   The blob is referenced, not copied (caller-owned; it may be shared by
+   contexts).  Errors: EINVAL (null ctx or blob, bytes other than
+   sldf_surrogate_blob_bytes(), blob not 256-byte aligned). */
+size_t sldf_surrogate_blob_bytes(void);
+sldf_status sldf_surrogate_load(sldf_ctx* ctx, const void* blob, size_t bytes);
 
 /* Monitoring (host-synchronous: call after the stream of the last run has
    completed): copies the per-frame count of uncertain pixels of the last

@@ -224,36 +224,52 @@ hipError_t launch_lidar_bits(const LidarArgs& a, int nframes, hipStream_t s)
 __global__ __launch_bounds__(256) void occlusion_kernel(const int16_t* dstar, uint16_t* x0, int W,
                                                         int H, int64_t px_stride)
 {
-    const int lane = threadIdx.x & 63;
-    const int y = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (y >= H) return;                          // uniform over the wave
-    const int64_t row = (int64_t)blockIdx.y * px_stride + (int64_t)y * W;
-    const int seg = (W + 63) / 64;
-    const int lo = min(lane * seg, W), hi = min(lo + seg, W);
-    constexpr int kNone = 1 << 20;               // no pixel to the right
-    int run_min = kNone;
-    for (int x = lo; x < hi; ++x) run_min = min(run_min, x - (int)dstar[row + x]);
-    // minimum over the runs of the lanes to the right (exclusive)
-    int incl = run_min;
+    // per wave: the row's d* and the margins, staged in LDS so that the
+    // global reads and writes go pixel by pixel across the lanes
+    extern __shared__ int16_t occ_lds[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int y = blockIdx.x * 4 + wv;
+    const bool live = y < H;                     // uniform over the wave
+    int16_t* sd = occ_lds + (size_t)wv * 2 * W;  // d*, then v in place
+    const int64_t row = (int64_t)blockIdx.y * px_stride + (int64_t)min(y, H - 1) * W;
+    if (live)
+        for (int x = lane; x < W; x += 64) sd[x] = dstar[row + x];
+    __syncthreads();
+    if (live) {
+        const int seg = (W + 63) / 64;
+        const int lo = min(lane * seg, W), hi = min(lo + seg, W);
+        constexpr int kNone = 1 << 20;           // no pixel to the right
+        int run_min = kNone;
+        for (int x = lo; x < hi; ++x) run_min = min(run_min, x - (int)sd[x]);
+        // minimum over the runs of the lanes to the right (exclusive)
+        int incl = run_min;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_down(incl, o, 64);
-        incl = lane + o < 64 ? min(incl, v) : incl;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_down(incl, o, 64);
+            incl = lane + o < 64 ? min(incl, v) : incl;
+        }
+        const int excl = __shfl_down(incl, 1, 64);
+        int m = lane < 63 ? excl : kNone;
+        int16_t* sv = sd + W;
+        for (int x = hi - 1; x >= lo; --x) {
+            const int q = x - (int)sd[x];
+            sv[x] = (int16_t)(q < 0 ? 16 : max(-16, min(16, q - m)));
+            m = min(m, q);
+        }
     }
-    const int excl = __shfl_down(incl, 1, 64);
-    int m = lane < 63 ? excl : kNone;
-    for (int x = hi - 1; x >= lo; --x) {
-        const int q = x - (int)dstar[row + x];
-        const int v = q < 0 ? 16 : max(-16, min(16, q - m));
-        x0[(row + x) * 8 + 5] = f32_to_bf16_rne((float)v * (1.0f / 16.0f));
-        m = min(m, q);
+    __syncthreads();
+    if (live) {
+        const int16_t* sv = sd + W;
+        for (int x = lane; x < W; x += 64)
+            x0[(row + x) * 8 + 5] = f32_to_bf16_rne((float)sv[x] * (1.0f / 16.0f));
     }
 }
 
 hipError_t launch_occlusion(const int16_t* dstar, uint16_t* x0, int W, int H, int64_t px_stride,
                             int nframes, hipStream_t s)
 {
-    hipLaunchKernelGGL(occlusion_kernel, dim3((H + 3) / 4, nframes), dim3(256), 0, s, dstar, x0,
+    const size_t lds = (size_t)4 * 2 * W * sizeof(int16_t);
+    hipLaunchKernelGGL(occlusion_kernel, dim3((H + 3) / 4, nframes), dim3(256), lds, s, dstar, x0,
                        W, H, px_stride);
     return hipGetLastError();
 }

@@ -914,6 +914,25 @@ sldf_status sldf_surrogate_set_weights(sldf_ctx* ctx, const uint16_t* weights,
     return SLDF_OK;
 }
 
+static size_t surrogate_bias_offset()
+{
+    return align_up((size_t)sldf_surrogate_num_weights() * 2, 256);
+}
+
+size_t sldf_surrogate_blob_bytes(void)
+{
+    return surrogate_bias_offset() + (size_t)sldf_surrogate_num_biases() * 4;
+}
+
+sldf_status sldf_surrogate_load(sldf_ctx* ctx, const void* blob, size_t bytes)
+{
+    if (!ctx || !blob || bytes != sldf_surrogate_blob_bytes() || ((uintptr_t)blob & 255))
+        return SLDF_EINVAL;
+    const char* b = static_cast<const char*>(blob);
+    return sldf_surrogate_set_weights(ctx, reinterpret_cast<const uint16_t*>(b),
+                                      reinterpret_cast<const float*>(b + surrogate_bias_offset()));
+}
+
 sldf_status sldf_fallback_read(sldf_ctx* ctx, int32_t* counts, int32_t n, int32_t* limit)
 {
     if (!ctx || !counts || !limit || n < 1 || n > ctx->p.batch) return SLDF_EINVAL;

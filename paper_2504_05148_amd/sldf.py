@@ -85,6 +85,8 @@ def lib():
         L.sldf_surrogate_num_weights.restype = _i32
         L.sldf_surrogate_num_biases.restype = _i32
         L.sldf_surrogate_set_weights.argtypes = [_vp, _vp, _vp]
+        L.sldf_surrogate_load.argtypes = [_vp, _vp, _sz]
+        L.sldf_surrogate_blob_bytes.restype = _sz
         L.sldf_surrogate_forward.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                              _vp, _vp]
         L.sldf_surrogate_train_workspace_size.argtypes = [_i32, _i32, _i32,
@@ -98,7 +100,7 @@ def lib():
                   "sldf_run", "sldf_run_batch", "sldf_lidar_quantize", "sldf_run_noalloc",
                   "sldf_timing_enable", "sldf_timing_read", "sldf_surrogate_set_weights",
                   "sldf_surrogate_forward", "sldf_surrogate_train_workspace_size",
-                  "sldf_surrogate_sync_weights",
+                  "sldf_surrogate_sync_weights", "sldf_surrogate_load",
                   "sldf_surrogate_train_step"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -236,6 +238,13 @@ class Context:
             self._h, _ptr(weights) if weights is not None else None,
             _ptr(biases) if biases is not None else None), "sldf_surrogate_set_weights")
 
+    def load_surrogate(self, blob: torch.Tensor):
+        """Attach learned-check parameters from one device blob
+        (surrogate_blob(weights, biases)); referenced, not copied."""
+        self._sur_keep = (blob,)
+        _check(lib().sldf_surrogate_load(self._h, _ptr(blob), blob.numel() * blob.element_size()),
+               "sldf_surrogate_load")
+
     def fallback_read(self, n: int):
         """(per-frame uncertain-pixel counts of the last learned run, limit);
         synchronises with the device."""
@@ -301,6 +310,19 @@ def run_noalloc(params: Params, left, right, lidar, disp, valid, stream=None):
 
 
 # ---------------------------------------------------------------- surrogate --
+def surrogate_blob(weights: torch.Tensor, biases: torch.Tensor) -> torch.Tensor:
+    """One device blob for sldf_surrogate_load: the bf16 weight bits, zero
+    padding to 256 bytes, the float32 biases (byte copies, no arithmetic)."""
+    n = int(lib().sldf_surrogate_blob_bytes())
+    blob = torch.zeros(n, dtype=torch.uint8, device=weights.device)
+    wb = weights.contiguous().view(torch.uint8).reshape(-1)
+    bb = biases.contiguous().view(torch.uint8).reshape(-1)
+    off = n - bb.numel()
+    blob[:wb.numel()] = wb
+    blob[off:] = bb
+    return blob
+
+
 def surrogate_sizes():
     return int(lib().sldf_surrogate_num_weights()), int(lib().sldf_surrogate_num_biases())
 

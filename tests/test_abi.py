@@ -166,6 +166,13 @@ def test_full_census_parameters():
     assert sldf.default_params().census_kind == 0
 
 
+def test_surrogate_blob_size():
+    """weights (bf16) padded to 256 bytes, then the float biases"""
+    L = sldf.lib()
+    nw, nb = L.sldf_surrogate_num_weights(), L.sldf_surrogate_num_biases()
+    assert L.sldf_surrogate_blob_bytes() == (nw * 2 + 255) // 256 * 256 + nb * 4
+
+
 def test_taps_struct_matches_header():
     """sldf_taps: twelve device pointers then the int32 direction of the
     single-path tap, in the header's order."""

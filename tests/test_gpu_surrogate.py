@@ -248,8 +248,8 @@ def test_train_step_deterministic_and_descends():
     assert losses[-1] < 0.9 * losses[0] and losses[-1] < entropy, (losses, entropy)
 
 
-# both path pass schedules (1 paired, 2 split), 4 and 8 paths
-SCHED_PATHS = [(1, 4), (2, 4), (1, 8), (2, 8)]
+# every path pass schedule (1 paired, 2 split, 3 two sweeps), 4 and 8 paths
+SCHED_PATHS = [(1, 4), (2, 4), (3, 4), (1, 8), (2, 8), (3, 8)]
 
 
 @pytest.mark.parametrize("schedule,paths", SCHED_PATHS)
@@ -275,6 +275,40 @@ def test_learned_run_matches_definition(schedule, paths):
     both = valid.bool() & base["valid"].bool()
     assert torch.equal(disp[both], base["disp"][both])
     assert (disp[~valid.bool()] == -1).all()
+
+
+def test_surrogate_blob_load_equals_attached_pointers():
+    """sldf_surrogate_load (one blob) runs the same network as
+    sldf_surrogate_set_weights; blobs of the wrong size or alignment are
+    rejected."""
+    f = synth.small_frame(2)
+    pkw = dict(width=f["W"], height=f["H"], max_disp=f["D"], census_w=5, census_h=5,
+               num_paths=8)
+    base = _features(f, pkw)
+    _, wbits, b = _params_bits(6)
+    wt = torch.from_numpy(wbits.view(np.int16)).cuda()
+    bt = torch.from_numpy(b).cuda()
+    p = sldf.default_params(check_impl=1, fallback_tau=1.0, uncertain_margin=0.0, **pkw)
+    outs = []
+    for use_blob in (False, True):
+        ctx = sldf.Context(p)
+        if use_blob:
+            blob = sldf.surrogate_blob(wt, bt)
+            ctx.load_surrogate(blob)
+            with pytest.raises(sldf.SldfError):
+                ctx.load_surrogate(blob[:-4])
+            with pytest.raises(sldf.SldfError):
+                ctx.load_surrogate(torch.zeros(blob.numel() + 16, dtype=torch.uint8,
+                                               device="cuda")[16:])
+            ctx.load_surrogate(blob)
+        else:
+            ctx.set_surrogate(wt, bt)
+        disp, valid = ctx.run(base["left"], base["right"], base["lid"])
+        torch.cuda.synchronize()
+        outs.append((disp.clone(), valid.clone()))
+        ctx.close()
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][0], outs[1][0])
 
 
 @pytest.mark.parametrize("schedule,paths", SCHED_PATHS)
