@@ -277,195 +277,6 @@ hipError_t launch_conv(const ConvArgs& a, int cin, int cout_pad, int nframes, hi
 }
 
 // ---------------------------------------------------------------------------
-// Layers 1 and 2 of the inference forward in one kernel: the layer-1
-// activations (8 -> 32 channels, dilation 1) never leave the chip.  A block
-// owns 64 output columns of one dilation-3 lattice of layer 2 and walks down
-// it like conv3x3_kernel<32, 2, 1>; each layer-2 input row (a layer-1 output
-// row, 70 columns with the halo) is computed in the block from three image
-// rows of the 8-channel input (72 columns), staged through a double buffer in
-// LDS, into the 4-slot ring of layer-1 rows.  Every layer-1 and layer-2
-// output sums the same k-steps in the same order as the separate layers, so
-// the results are bit-identical; the block reads 3 x 16 B of input per
-// layer-1 row pixel instead of reading and writing the 64 B activations.
-// ---------------------------------------------------------------------------
-constexpr int kC12Tw = 64;                       // output columns per block
-constexpr int kC12D = 3;                         // layer-2 dilation
-constexpr int kC12A = kC12Tw + 2 * kC12D;        // layer-1 columns per row (70)
-constexpr int kC12X = kC12A + 2;                 // input columns per row (72)
-constexpr int kC12Ahead = 2;                     // layer-1 rows of input in flight
-
-__global__ __launch_bounds__(256) void conv12_kernel(Conv12Args a, int ntx, int qblocks,
-                                                     int rows_blk, int nframes)
-{
-    __shared__ uint4 ring[kConvSlots][kC12A * 4];    // layer-1 rows, swizzled 16 B chunks
-    __shared__ uint4 xb[2][3][kC12X];                // input rows of one layer-1 row
-    const int d = kC12D;
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int logical = (b % 8) * (nb / 8) + b / 8;
-    const int per_frame = ntx * d * qblocks;
-    const int frame = logical / per_frame;
-    if (frame >= nframes) return;
-    const int rem = logical - frame * per_frame;
-    const int yb = rem / ntx, tx = rem - yb * ntx;
-    const int r = yb / qblocks, qb = yb - r * qblocks;
-    const int x0 = tx * kC12Tw;
-    const int nrows = min(rows_blk, (a.H - r + d - 1) / d - qb * rows_blk);
-    if (nrows <= 0) return;
-    const uint16_t* x = a.x + (int64_t)frame * a.px_stride * 8;
-    const int ybase = r + d * (qb * rows_blk - 1);   // layer-1 row k is ybase + d k
-
-    // the three input rows of layer-1 row k: one 16-byte pixel per thread
-    const int tid = threadIdx.x;
-    const int lrow = tid / kC12X, lpx = tid - lrow * kC12X;   // tid < 216 loads
-    auto load_in = [&](int k) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (tid < 3 * kC12X) {
-            const int sy = ybase + d * min(k, nrows + 1) - 1 + lrow;
-            const int sx = x0 - d - 1 + lpx;
-            if (sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
-                v = *reinterpret_cast<const uint4*>(x + ((int64_t)sy * a.W + sx) * 8);
-        }
-        return v;
-    };
-    auto store_in = [&](int k, uint4 v) {
-        if (tid < 3 * kC12X) xb[k & 1][lrow][lpx] = v;
-    };
-
-    const int lane = tid & 63, wave = tid >> 6;
-    const int j = lane & 15, g = lane >> 4;
-    // weights of both layers (A operands) and the lanes' biases
-    uint4 av1[3][2], av2[9][2];
-#pragma unroll
-    for (int ks = 0; ks < 3; ++ks) {
-        const int tap = 4 * ks + g;
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-            av1[ks][mt] = tap < 9 ? *reinterpret_cast<const uint4*>(a.w1 + (tap * 32 + 16 * mt + j) * 8)
-                                  : make_uint4(0, 0, 0, 0);
-    }
-#pragma unroll
-    for (int ks = 0; ks < 9; ++ks)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-            av2[ks][mt] = *reinterpret_cast<const uint4*>(a.w2 + (ks * 32 + 16 * mt + j) * 32 + 8 * g);
-    float bias1[2][4], bias2[2][4];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            bias1[mt][e] = a.b1[16 * mt + 4 * g + e];
-            bias2[mt][e] = a.b2[16 * mt + 4 * g + e];
-        }
-
-    // packs the lane's 8 outputs (channels 4g..4g+3, 16+4g..16+4g+3 of pixel
-    // j) after bias and ReLU into the 16 bytes of channel chunk
-    // ((g & 1) << 1) | (g >> 1) of the same pixel (one permlane16 swap)
-    auto pack = [&](const f32x4 (&acc)[2], const float (&bias)[2][4]) {
-        float v[2][4];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                v[mt][e] = acc[mt][e] + bias[mt][e];
-                v[mt][e] = v[mt][e] > 0.f ? v[mt][e] : 0.f;
-            }
-        const uint32_t A0 = bf16_rne(v[0][0]) | ((uint32_t)bf16_rne(v[0][1]) << 16);
-        const uint32_t A1 = bf16_rne(v[0][2]) | ((uint32_t)bf16_rne(v[0][3]) << 16);
-        const uint32_t B0 = bf16_rne(v[1][0]) | ((uint32_t)bf16_rne(v[1][1]) << 16);
-        const uint32_t B1 = bf16_rne(v[1][2]) | ((uint32_t)bf16_rne(v[1][3]) << 16);
-        const auto s0 = __builtin_amdgcn_permlane16_swap(A0, B0, false, false);
-        const auto s1 = __builtin_amdgcn_permlane16_swap(A1, B1, false, false);
-        return make_uint4(s0[0], s1[0], s0[1], s1[1]);
-    };
-    const int chunk = ((g & 1) << 1) | (g >> 1);
-
-    // layer-1 row k (input staged in xb[k & 1]) into its ring slot; zero
-    // outside the image (layer 2's padding)
-    auto layer1 = [&](int k) {
-        const int ya = ybase + d * k;
-        const bool rin = ya >= 0 && ya < a.H;
-        uint4* slot = ring[k % kConvSlots];
-        for (int t = wave; t * 16 < kC12A; t += 4) {
-            f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int ks = 0; ks < 3; ++ks) {
-                const int tap = 4 * ks + g;
-                const int ky = tap / 3, kx = tap % 3;
-                const int px = t * 16 + j + kx;          // input column of this tap
-                uint4 bv = make_uint4(0, 0, 0, 0);
-                if (tap < 9 && px < kC12X) bv = xb[k & 1][ky][px];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) acc[mt] = mfma16(av1[ks][mt], bv, acc[mt]);
-            }
-            const uint4 o = pack(acc, bias1);
-            const int pa = t * 16 + j;                   // layer-1 column in the row
-            const int sx = x0 - d + pa;
-            const bool in = rin && sx >= 0 && sx < a.W;
-            if (pa < kC12A) slot[swz<4>(pa, chunk)] = in ? o : make_uint4(0, 0, 0, 0);
-        }
-    };
-
-    // prologue: layer-1 rows 0, 1, 2 in the ring, the input of row 3 staged,
-    // rows 4 .. 3 + kC12Ahead in flight
-    for (int k = 0; k < 3; ++k) {
-        store_in(k, load_in(k));
-        __syncthreads();
-        layer1(k);
-        __syncthreads();
-    }
-    store_in(3, load_in(3));
-    uint4 q[kC12Ahead];
-#pragma unroll
-    for (int k = 0; k < kC12Ahead; ++k) q[k] = load_in(4 + k);
-    __syncthreads();
-
-    for (int i0 = 0; i0 < nrows; i0 += kC12Ahead) {
-#pragma unroll
-        for (int jj = 0; jj < kC12Ahead; ++jj) {
-            const int i = i0 + jj;
-            // stage the input of layer-1 row i + 4, fetch that of i + 4 + ahead
-            store_in(i + 4, q[jj]);
-            q[jj] = load_in(i + 4 + kC12Ahead);
-            // layer-1 row i + 3 (its input was staged one step ago)
-            layer1(i + 3);
-            // layer-2 output row i from layer-1 rows i, i + 1, i + 2
-            f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-            for (int ks = 0; ks < 9; ++ks) {
-                const int ky = ks / 3, kx = ks % 3;
-                const uint4* slot = ring[(i + ky) % kConvSlots];
-                const uint4 bv = slot[swz<4>(wave * 16 + j + kx * d, g)];
-#pragma unroll
-                for (int mt = 0; mt < 2; ++mt) acc[mt] = mfma16(av2[ks][mt], bv, acc[mt]);
-            }
-            const uint4 o = pack(acc, bias2);
-            const int y = r + d * (qb * rows_blk + i);
-            const int px = x0 + wave * 16 + j;
-            if (i < nrows && px < a.W) {
-                const int64_t p = (int64_t)frame * a.px_stride + (int64_t)y * a.W + px;
-                *reinterpret_cast<uint4*>(a.y + p * 32 + 8 * chunk) = o;
-            }
-            __syncthreads();
-        }
-    }
-}
-
-hipError_t launch_conv12(const Conv12Args& a, int nframes, hipStream_t s)
-{
-    const int d = kC12D;
-    const int ntx = (a.W + kC12Tw - 1) / kC12Tw;
-    const int lattice_rows = (a.H + d - 1) / d;
-    const int rows_max = nframes == 1 ? 8 : kConvRowsMax;
-    const int qblocks = (lattice_rows + rows_max - 1) / rows_max;
-    const int rows_blk = (lattice_rows + qblocks - 1) / qblocks;
-    const int64_t nb = (int64_t)ntx * d * qblocks * nframes;
-    dim3 grid((unsigned)((nb + 7) / 8 * 8));
-    hipLaunchKernelGGL(conv12_kernel, grid, dim3(256), 0, s, a, ntx, qblocks, rows_blk, nframes);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // dgrad weights: Wt[tap][i][o] = W[8 - tap][o][i]  (the flipped tap set is
 // the mirrored 3x3 offset grid), zero-padded to the target shape.
 // ---------------------------------------------------------------------------

@@ -735,20 +735,8 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         // learned check: CNN on the surrogate inputs, then the mask
         const uint16_t* w = ctx->sur_w;
         const float* bb = ctx->sur_b;
-        // layers 1 and 2 in one launch (the layer-1 activations stay on chip)
-        Conv12Args c12;
-        c12.x = b.x0;
-        c12.w1 = w + kSurOffW1;
-        c12.b1 = bb + kSurOffB1;
-        c12.w2 = w + kSurOffW2;
-        c12.b2 = bb + kSurOffB2;
-        c12.y = b.act[1];
-        c12.px_stride = b.px_stride;
-        c12.W = W;
-        c12.H = H;
-        if (launch_conv12(c12, n_frames, s) != hipSuccess) return SLDF_EDEVICE;
-        const uint16_t* in = b.act[1];
-        for (int l = 2; l < 4; ++l) {
+        const uint16_t* in = b.x0;
+        for (int l = 0; l < 4; ++l) {
             ConvArgs cv;
             cv.x = in;
             cv.w = w + (l == 0 ? kSurOffW1 : l == 1 ? kSurOffW2 : l == 2 ? kSurOffW3 : kSurOffW4);
@@ -781,7 +769,7 @@ sldf_status sldf_run_batch(sldf_ctx* ctx, int32_t n_frames, const uint8_t* left,
         ma.tc = p.tc;
         ma.margin = p.uncertain_margin;
         if (launch_learned_mask(ma, n_frames, s) != hipSuccess) return SLDF_EDEVICE;
-        ctx->launches[3] += 4;
+        ctx->launches[3] += 5;
         if (mark(4) != hipSuccess) return SLDF_EDEVICE;
         // fallback: frames with too many uncertain pixels run the right-view
         // SGM and the plain check (every block tests the device counter)

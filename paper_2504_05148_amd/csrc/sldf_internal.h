@@ -212,18 +212,6 @@ struct ConvArgs {
     int32_t W, H, dil, relu, cout;
 };
 
-// layers 1 and 2 of the inference forward in one launch (k_surrogate.hip)
-struct Conv12Args {
-    const uint16_t* x;        // NHWC bf16 input [F][H][W][8]
-    const uint16_t* w1;       // [9][32][8] bf16
-    const float* b1;          // [32]
-    const uint16_t* w2;       // [9][32][32] bf16
-    const float* b2;          // [32]
-    uint16_t* y;              // NHWC bf16 layer-2 output [F][H][W][32]
-    int64_t px_stride;
-    int32_t W, H;
-};
-
 struct WgradArgs {
     const uint16_t* x;        // layer input NHWC [F][H][W][cin]
     const uint16_t* g;        // output gradient NHWC [F][H][W][gc]
@@ -283,7 +271,6 @@ hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_sync_weights(const float* master, uint16_t* w_bf16, float* bias, hipStream_t s);
 hipError_t launch_learned_mask(const MaskArgs& a, int nframes, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int v, hipStream_t s);
-hipError_t launch_conv12(const Conv12Args& a, int nframes, hipStream_t s);
 
 // path pass roles: the first pass stores S, middle ones add into it, the
 // last takes the WTA; kMiddle2 also adds the second term S2 of a split pass
