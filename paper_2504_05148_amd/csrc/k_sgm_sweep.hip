@@ -219,7 +219,11 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                         // until the row has walked down to a multiple of 2G
                         SweepStage<G>& rs = ostage[j];
                         const int slot = x % (2 * G);
-                        const WtaStage ws{&rs.d[slot], &rs.v[slot], &rs.f[2 * slot]};
+                        typedef __attribute__((address_space(3))) int16_t li16;
+                        typedef __attribute__((address_space(3))) float lf32;
+                        typedef __attribute__((address_space(3))) uint32_t lu32;
+                        const WtaStage ws{true, (li16*)&rs.d[slot], (lf32*)&rs.v[slot],
+                                          (lu32*)&rs.f[2 * slot]};
                         wta_emit<G, VIEW, NR>(a, St, d0, 0, reinterpret_cast<const uint16_t*>(srow),
                                               ws);
                         if (slot == 0) {

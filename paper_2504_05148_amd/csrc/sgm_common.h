@@ -363,14 +363,15 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
     m = group_min<G>(lane_min<NR>(L));
 }
 
-// Where wta_emit puts the owner lane's outputs of a pixel: null d writes them
-// to global memory at px; otherwise to these LDS slots (d*, the subpixel
+// Where wta_emit puts the owner lane's outputs of a pixel: with on false, to
+// global memory at px; otherwise to these LDS slots (d*, the subpixel
 // disparity and the two cost-feature words), which the caller writes out
 // later with other pixels of the row in whole cache lines.
 struct WtaStage {
-    int16_t* d = nullptr;
-    float* v = nullptr;
-    uint32_t* f = nullptr;
+    bool on = false;
+    __attribute__((address_space(3))) int16_t* d = nullptr;
+    __attribute__((address_space(3))) float* v = nullptr;
+    __attribute__((address_space(3))) uint32_t* f = nullptr;
 };
 
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
@@ -409,7 +410,7 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
         second = group_min<G>(second);
     }
     if (db >= d0 && db < d0 + K) {
-        if (stage.d) stage.d[0] = (int16_t)db;
+        if (stage.on) stage.d[0] = (int16_t)db;
         else a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
             uint32_t A = 0, B = best >> 9, Cc = 0;   // S(d*) is the minimum itself
@@ -441,7 +442,7 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
                 v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
             const uint32_t f0 = B | (second << 16);
             const uint32_t f1 = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
-            if (stage.d) {
+            if (stage.on) {
                 stage.v[0] = v;
                 stage.f[0] = f0;
                 stage.f[1] = f1;
