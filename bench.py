@@ -127,10 +127,14 @@ def _cpu_model():
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
     except (OSError, subprocess.SubprocessError):
         return None
+    keys = {"Model name": "model", "CPU(s)": "cpus", "Thread(s) per core": "threads_per_core",
+            "Socket(s)": "sockets", "CPU max MHz": "max_mhz"}
+    info = {}
     for line in out.splitlines():
-        if line.startswith("Model name:"):
-            return line.split(":", 1)[1].strip()
-    return None
+        k, _, v = line.partition(":")
+        if k.strip() in keys and keys[k.strip()] not in info:
+            info[keys[k.strip()]] = v.strip()
+    return info or None
 
 
 def _oracle_frames(kind, idxs):
@@ -165,7 +169,7 @@ def cpu_baseline(n_frames: int, n_small: int, all_cores: bool):
                sample=f"{n_frames} synthetic 1242x375 D=128 frames, full method (9x7 census, "
                       f"8 paths, SDSGM, stereo-LiDAR check), single-threaded C oracle "
                       f"({dt:.1f} s)",
-               cpu_model=_cpu_model())
+               cpu_lscpu=_cpu_model())
     if n_small > 0:
         ds = _oracle_time("small", range(1000, 1000 + n_small))
         out["small_frames"] = dict(value=round(n_small / ds, 3), unit="frames/s", cores=1,
