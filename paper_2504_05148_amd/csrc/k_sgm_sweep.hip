@@ -479,23 +479,21 @@ static int rows_of(int D, int nw)
     return (nw - 1) * (64 / (D / 8));
 }
 
-// Workgroup size and bands of a launch: 16-wave workgroups (15 waves of rows,
-// one per compute unit: they fill its LDS), the rows spread evenly over the
-// fewest bands.  (Two 8-wave workgroups per unit, whose barriers do not run
-// in step, measured no faster.)
-SweepPlan sweep_plan(int W, int H, int D, int64_t n_fv)
+// Bands of a frame-view: 16-wave workgroups (15 waves of rows, one
+// workgroup per compute unit: they fill its LDS), the rows spread evenly over
+// the fewest bands.  (Two 8-wave workgroups per unit, whose barriers do not
+// run in step, measured no faster.)
+SweepPlan sweep_plan(int H, int D)
 {
-    (void)W;
-    (void)n_fv;
     const int rpw = 64 / (D / 8);
     const int bands = (H + rows_of(D, kSwWaves) - 1) / rows_of(D, kSwWaves);
     const int per = (H + bands - 1) / bands;
-    return SweepPlan{kSwWaves, bands, (per + rpw - 1) / rpw * rpw};
+    return SweepPlan{bands, (per + rpw - 1) / rpw * rpw};
 }
 
 int64_t sweep_hand_bytes_per_fv(int W, int H, int D)
 {
-    const int nb = sweep_plan(W, H, D, 1).bands;
+    const int nb = sweep_plan(H, D).bands;
     const int recp = D == 64 ? sweep_rec_pad<8>() : D == 128 ? sweep_rec_pad<16>() : sweep_rec_pad<32>();
     return (int64_t)(nb - 1) * W * recp * 16;
 }
@@ -506,7 +504,7 @@ hipError_t launch_sgm_sweep(const SgmArgs& a0, int D, int pass, int nviews, int 
     SgmArgs a = a0;
     a.nviews = nviews;
     a.n_fv = nviews * nframes;
-    const SweepPlan pl = sweep_plan(a.W, a.H, D, a.n_fv);
+    const SweepPlan pl = sweep_plan(a.H, D);
     a.blocks_per_fv = pl.bands;                  // bands per frame-view
     a.rows_per_band = pl.rows_per_band;
     const int np = a.npaths;                     // 4 or 8

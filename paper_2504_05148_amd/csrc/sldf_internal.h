@@ -303,14 +303,12 @@ constexpr int kSplitFrames = 1;
 // takes the WTA.  a.npaths is 4 or 8; a.hand / a.sync as in SgmArgs.
 hipError_t launch_sgm_sweep(const SgmArgs& a, int D, int pass, int nviews, int nframes,
                             hipStream_t s);
-// workgroup size (waves), row bands per frame-view and rows per band of a
-// launch over n_fv frame-views
+// row bands per frame-view and rows per band of the two-sweep schedule
 struct SweepPlan {
-    int nw;
     int bands;
     int rows_per_band;
 };
-SweepPlan sweep_plan(int W, int H, int D, int64_t n_fv);
+SweepPlan sweep_plan(int H, int D);
 int64_t sweep_hand_bytes_per_fv(int W, int H, int D);
 // runs of at least this many frames take the two-sweep schedule by default
 // (smaller runs leave the machine idle along the sweeps' row skew and are
