@@ -1,4 +1,4 @@
-// Learned consistency surrogate: a 4-layer 3x3 CNN (5 -> 32 -> 32 -> 32 -> 1
+// Learned consistency surrogate: a 4-layer 3x3 CNN (6 -> 32 -> 32 -> 32 -> 1
 // channels, dilations 1, 3, 9, 27, ReLU between layers) that predicts the
 // validity mask of the stereo-LiDAR check (Eq. 6) from left-view cost
 // features, so that the right-view SGM pass can be skipped.  BF16 weights and
@@ -7,9 +7,9 @@
 //
 // Convolution = implicit GEMM per 16-pixel row tile:
 //   D[oc][px] += W[oc][k] * X[k][px],  k = (tap, input channel)
-// A operand (16 output channels x 32 k) comes from the LDS copy of the
-// weights, B operand (32 k x 16 pixels) is one 16-byte load of 8 input
-// channels of one neighbour pixel (NHWC).  With 32 input channels one k-step
+// A operand (16 output channels x 32 k): the weights, held in registers for
+// a whole block; B operand (32 k x 16 pixels): one 16-byte LDS read of 8
+// input channels of one neighbour pixel (NHWC).  With 32 input channels one k-step
 // is one tap; with 8 input channels one k-step covers four taps.
 // Backward: dgrad is the same convolution with tap-flipped, channel-
 // transposed weights and the ReLU gate of the layer input; wgrad is an MFMA
