@@ -171,6 +171,12 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
             }
             const vecT<NR> sa = SA[i];
             const int inext = (i + 1) % kRing;
+            // sweep A: ring slot i (this step's inputs, consumed at the end of
+            // the step before) takes those of step t + kRing, issued before this
+            // step's S store, so that waiting for them never waits for that store
+            // (loads and stores share one counter); sweep B, short of registers,
+            // loads at the end of the step
+            if (!kLast) load(i, sw_pos(t + kRing, j));
             if (!skip) {
                 // Eq. 2 for each direction of the set: h, dn and dr first (their
                 // inputs are in registers), dl last (it needs this step's read)
@@ -284,7 +290,7 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                 mdrq2 = mdrq1;
                 mdrq1 = mdrn;
             }
-            load(i, sw_pos(t + kRing, j));
+            if (kLast) load(i, sw_pos(t + kRing, j));
             __syncthreads();
         }
     }
