@@ -25,3 +25,21 @@ def test_batch_must_split_over_streams():
     assert r.returncode == 2
     assert "--streams" in r.stderr
     assert r.stdout == ""
+
+
+def test_committed_traffic_profile_matches_kernel_sources():
+    """The HBM-traffic record the bench reports was taken on the committed
+    sources of the sweep kernel (else the bench reports traffic as null)."""
+    import hashlib
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    rec = json.load(open(os.path.join(root, "profiles", "sgm_sweep_kernel_traffic.json")))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(root, src), "rb").read())
+    assert rec["source_sha256"] == h.hexdigest()
+    assert rec["frames_per_launch"] == 64
+    # the summary it names exists and quotes the same total
+    summ = open(os.path.join(root, "profiles", rec["summary"])).read()
+    assert f"{rec['traffic_bytes_per_launch'] / 1e9:.2f} GB per launch" in summ
