@@ -397,17 +397,26 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
     const int db = (int)(best & 511u);
     const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[NR - 1]);
     const uint32_t snx = simg ? 0u : dpp<kWaveShl1>(St[0]);
-    // learned-check cost feature: second minimum of S over |d - d*| >= 2
+    // learned-check cost feature: second minimum of S over |d - d*| >= 2.  The
+    // lane's cells d* - 1 .. d* + 1 (local indices e - 1 .. e + 1, e = d* - d0)
+    // are set to 0xffff in packed form before a packed minimum: bits of the
+    // 3-bit window shifted into place, two bits per register spread to the
+    // two u16 halves.  An S of 0xffff elsewhere gives the same minimum.
     uint32_t second = 0xffffu;
     if (VIEW == 0 && a.feat) {
+        const int e = db - d0;
+        const uint32_t win = (e >= -1 && e <= K) ? ((0x7u << (e + 7)) >> 8) : 0u;
+        uint32_t mn = 0xffffffffu;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const int d_lo = d0 + 2 * i, d_hi = d_lo + 1;
-            const uint32_t s_lo = St[i] & 0xffffu, s_hi = St[i] >> 16;
-            second = (d_lo - db >= 2 || db - d_lo >= 2) ? min(second, s_lo) : second;
-            second = (d_hi - db >= 2 || db - d_hi >= 2) ? min(second, s_hi) : second;
+            // bits 2i and 2i + 1 sign-extended to 0 / all ones, their low
+            // halves packed into one word
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_sbfe((int)win, 2 * i, 1);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_sbfe((int)win, 2 * i + 1, 1);
+            const uint32_t gate = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+            mn = pk_min(mn, St[i] | gate);
         }
-        second = group_min<G>(second);
+        second = group_min<G>(min(mn & 0xffffu, mn >> 16));
     }
     if (db >= d0 && db < d0 + K) {
         if (stage.on) stage.d[0] = (int16_t)db;
