@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=125)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=64, help="frames per step")
+    ap.add_argument("--batch", type=int, default=128, help="frames per step")
     ap.add_argument("--streams", type=int, default=2,
                     help="the step's frames are split over this many contexts, each on its "
                          "own stream (throughput mode); the roofline and the stage times "
@@ -479,42 +479,44 @@ def main():
               file=sys.stderr, flush=True)
 
     # throughput over frames per call x streams (one context per stream, the
-    # 16 generated frames repeated to fill larger calls), plain check
+    # generated frames repeated to fill larger calls), plain check
     sweep = []
     if args.sweep_frames > 0:
-        for kf in (1, 4, 8, 16, 32, 64):
-            for ns in (1, 2):
-                idx = torch.arange(kf, device="cuda") % B
-                # gather on the padded buffers, so that rows keep the 16-byte pitch
-                pad = (B, H, left.stride(1))
-                lk = left.as_strided(pad, left.stride())[idx][:, :, :W]
-                rk = right.as_strided(pad, right.stride())[idx][:, :, :W]
-                fk = lid_f[idx].contiguous()
-                ctxs = [sldf.Context(sldf.default_params(batch=kf)) for _ in range(ns)]
-                outs = [c.new_outputs(kf) for c in ctxs]
-                lqs = [torch.empty((kf, H, W), dtype=torch.int16, device="cuda")
-                       for _ in range(ns)]
-                streams = [stream] + [torch.cuda.Stream() for _ in range(ns - 1)]
+        # frames per call x streams; 128 frames per call on one stream only (two
+        # such contexts would not fit beside the ones the steps above hold)
+        pairs = [(kf, ns) for kf in (1, 4, 8, 16, 32, 64) for ns in (1, 2)] + [(128, 1)]
+        for kf, ns in pairs:
+            idx = torch.arange(kf, device="cuda") % B
+            # gather on the padded buffers, so that rows keep the 16-byte pitch
+            pad = (B, H, left.stride(1))
+            lk = left.as_strided(pad, left.stride())[idx][:, :, :W]
+            rk = right.as_strided(pad, right.stride())[idx][:, :, :W]
+            fk = lid_f[idx].contiguous()
+            ctxs = [sldf.Context(sldf.default_params(batch=kf)) for _ in range(ns)]
+            outs = [c.new_outputs(kf) for c in ctxs]
+            lqs = [torch.empty((kf, H, W), dtype=torch.int16, device="cuda")
+                   for _ in range(ns)]
+            streams = [stream] + [torch.cuda.Stream() for _ in range(ns - 1)]
 
-                def round_():
-                    for i in range(ns):
-                        sldf.quantize_lidar(fk.view(kf * H, W), D, out=lqs[i].view(kf * H, W),
-                                            stream=streams[i])
-                        ctxs[i].run_batch(lk, rk, lqs[i], outs[i][0], outs[i][1],
-                                          stream=streams[i])
+            def round_():
+                for i in range(ns):
+                    sldf.quantize_lidar(fk.view(kf * H, W), D, out=lqs[i].view(kf * H, W),
+                                        stream=streams[i])
+                    ctxs[i].run_batch(lk, rk, lqs[i], outs[i][0], outs[i][1],
+                                      stream=streams[i])
 
-                rounds = max(1, -(-args.sweep_frames // (kf * ns)))
-                for _ in range(2):
-                    round_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(rounds):
-                    round_()
-                torch.cuda.synchronize()
-                el_s = time.perf_counter() - t0
-                sweep.append(dict(frames_per_call=kf, streams=ns,
-                                  frames_per_s=round(rounds * kf * ns / el_s, 1)))
-                del ctxs, outs, lqs, lk, rk, fk
+            rounds = max(1, -(-args.sweep_frames // (kf * ns)))
+            for _ in range(2):
+                round_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(rounds):
+                round_()
+            torch.cuda.synchronize()
+            el_s = time.perf_counter() - t0
+            sweep.append(dict(frames_per_call=kf, streams=ns,
+                              frames_per_s=round(rounds * kf * ns / el_s, 1)))
+            del ctxs, outs, lqs, lk, rk, fk
         torch.cuda.empty_cache()
         print(f"[bench] sweep {sweep}", file=sys.stderr, flush=True)
 

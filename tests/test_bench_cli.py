@@ -39,7 +39,7 @@ def test_committed_traffic_profile_matches_kernel_sources():
     for src in rec["sources"]:
         h.update(open(os.path.join(root, src), "rb").read())
     assert rec["source_sha256"] == h.hexdigest()
-    assert rec["frames_per_launch"] == 64
+    assert rec["frames_per_launch"] == 128
     # the summary it names exists and quotes the same total
     summ = open(os.path.join(root, "profiles", rec["summary"])).read()
     assert f"{rec['traffic_bytes_per_launch'] / 1e9:.2f} GB per launch" in summ
