@@ -81,12 +81,14 @@ __device__ __forceinline__ int sw_pos(int t, int j) { return t - 2 * j; }
 
 // The outputs of the last 2G pixels of a row in the second sweep (LDS),
 // written to global memory 2G at a time (whole lines instead of one scattered
-// 2- or 4-byte store per pixel)
+// 2- or 4-byte store per pixel); the subpixel division is taken there too,
+// two pixels per lane, instead of once per step by the whole wave for its
+// owner lanes
 template <int G>
 struct SweepStage {
     int16_t d[2 * G];
-    float v[2 * G];
-    uint32_t f[4 * G];
+    int32_t num[2 * G];     // S(d*-1) - S(d*+1)
+    uint32_t f[4 * G];      // cost-feature words; f[2i + 1] is the parabola's denominator
 };
 
 template <int G, int PASS, int NP, int VIEW, int NW>
@@ -113,6 +115,9 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
     // their row (u < 0), past it by more than one pixel, or outside the band
     // / image is skipped as a whole (states stay zero before the row; the dl
     // output at u = W, the last one the row below reads, is still written)
+    // the feature switch as a scalar (the compiler otherwise rebuilds it from
+    // a lane mask in every step)
+    const bool want_feat = __builtin_amdgcn_readfirstlane(a.feat != nullptr ? 1 : 0) != 0;
     const int j0 = j - j % RPW;
     const bool wave_dead = j0 >= rpb || band * rpb + j0 >= a.H;
     Edge edge;
@@ -224,12 +229,12 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                         // the pixel's outputs wait in the row's stage (slot x mod 2G)
                         // until the row has walked down to a multiple of 2G
                         SweepStage<G>& rs = ostage[j];
-                        const int slot = x % (2 * G);
+                        const int slot = (int)((uint32_t)x % (2u * G));   // x >= 0 here
                         typedef __attribute__((address_space(3))) int16_t li16;
-                        typedef __attribute__((address_space(3))) float lf32;
+                        typedef __attribute__((address_space(3))) int32_t li32;
                         typedef __attribute__((address_space(3))) uint32_t lu32;
-                        const WtaStage ws{true, (li16*)&rs.d[slot], (lf32*)&rs.v[slot],
-                                          (lu32*)&rs.f[2 * slot]};
+                        const WtaStage ws{true, want_feat, (li16*)&rs.d[slot],
+                                          (li32*)&rs.num[slot], (lu32*)&rs.f[2 * slot]};
                         wta_emit<G, VIEW, NR>(a, St, d0, 0, reinterpret_cast<const uint16_t*>(srow),
                                               ws);
                         if (slot == 0) {
@@ -242,8 +247,9 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                                     const size_t p = rowp + x + i;
                                     a.wta[VIEW][p] = rs.d[i];
                                     if (VIEW == 0) {
-                                        a.dsub[p] = rs.v[i];
-                                        if (a.feat) {
+                                        a.dsub[p] = subpixel_value(a.subpixel, rs.d[i], rs.num[i],
+                                                                   (int)rs.f[2 * i + 1]);
+                                        if (want_feat) {
                                             a.feat[2 * p] = rs.f[2 * i];
                                             a.feat[2 * p + 1] = rs.f[2 * i + 1];
                                         }

@@ -49,6 +49,14 @@ __device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c)
     asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
+// |a - b| + c in one instruction (both operands below 2^31 here, so the
+// signed and unsigned readings of the difference agree)
+__device__ __forceinline__ uint32_t sad(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 __device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b) { return u1(v2(a) - v2(b)); }
 // Three-way packed minimum of u16 values below 0x7c00: such bit patterns
 // are positive finite fp16 numbers (denormals included, which the kernels
@@ -350,29 +358,43 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
     for (int i = 1; i < NR; ++i) Dm[i] = __builtin_amdgcn_alignbit(L[i], L[i - 1], 16);
     Dm[NR] = __builtin_amdgcn_alignbit(nx, L[NR - 1], 16);
     const uint32_t mp2 = pk_add(m, p2x2);
-    // best + C - m in one 32-bit three-way add: in each half best >= m (every
-    // term of the minimum is at least m) and the result lies in [0, 0xffff],
-    // so the 32-bit sum of best, C and -(m, m) equals the packed one
-    const uint32_t negm = 0u - m;
+    // best - m + C in one 32-bit instruction |best - m| + C: in each half
+    // best >= m (every term of the minimum is at least m), so the 32-bit
+    // difference borrows nothing across the halves, and the result lies in
+    // [0, 0xffff] per half: it equals the packed one
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
         uint32_t nb = pk_add(pk_min(Dm[i], Dm[i + 1]), p1x2);
         uint32_t best = pk_min3(L[i], nb, mp2);
-        L[i] = add3(best, C[i], negm);
+        L[i] = sad(best, m, C[i]);
     }
     m = group_min<G>(lane_min<NR>(L));
 }
 
 // Where wta_emit puts the owner lane's outputs of a pixel: with on false, to
-// global memory at px; otherwise to these LDS slots (d*, the subpixel
-// disparity and the two cost-feature words), which the caller writes out
-// later with other pixels of the row in whole cache lines.
+// global memory at px; otherwise to these LDS slots (d*, the numerator of
+// the parabola offset and the two cost-feature words, the second of which
+// is its denominator), which the caller writes out later with other pixels
+// of the row in whole cache lines, taking the division there.
 struct WtaStage {
     bool on = false;
+    bool feat = false;      // with on: the cost features are wanted (a.feat not null)
     __attribute__((address_space(3))) int16_t* d = nullptr;
-    __attribute__((address_space(3))) float* v = nullptr;
+    __attribute__((address_space(3))) int32_t* num = nullptr;
     __attribute__((address_space(3))) uint32_t* f = nullptr;
 };
+
+// Subpixel disparity of the parabola through S(d*-1), S(d*), S(d*+1):
+// d* + num / (2 den) with num = S(d*-1) - S(d*+1) and den = S(d*-1) - 2 S(d*)
+// + S(d*+1), passed as 0 at the ends of the disparity range; no refinement
+// there or for a flat parabola (den is never negative at the minimum).  One
+// correctly rounded float division of exact integers, then one float add.
+__device__ __forceinline__ float subpixel_value(int subpixel, int db, int num, int den)
+{
+    float v = (float)db;
+    if (subpixel && den > 0) v = (float)db + __fdiv_rn((float)num, (float)(2 * den));
+    return v;
+}
 
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
 // of (S, d), ties -> smallest d) and the parabola fit through S(d*-1),
@@ -386,15 +408,18 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
                                          const WtaStage& stage = WtaStage{})
 {
     constexpr int K = 2 * NR, D = G * K;
+    // keys S << 16 | e over the lane's cells e, then d0 added to the lane's
+    // minimum: the smallest key is the smallest S and, among equal S, the
+    // smallest d = d0 + e
     uint32_t best = 0xffffffffu;
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        uint32_t k0 = ((St[i] & 0xffffu) << 9) | (uint32_t)(d0 + 2 * i);
-        uint32_t k1 = ((St[i] >> 16) << 9) | (uint32_t)(d0 + 2 * i + 1);
+        const uint32_t k0 = (St[i] << 16) | (uint32_t)(2 * i);
+        const uint32_t k1 = (St[i] & 0xffff0000u) | (uint32_t)(2 * i + 1);
         best = min(best, min(k0, k1));
     }
-    best = group_min<G>(best);
-    const int db = (int)(best & 511u);
+    best = group_min<G>(best + (uint32_t)d0);
+    const int db = (int)(best & 0xffffu);
     const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[NR - 1]);
     const uint32_t snx = simg ? 0u : dpp<kWaveShl1>(St[0]);
     // learned-check cost feature: second minimum of S over |d - d*| >= 2.  The
@@ -403,7 +428,7 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
     // 3-bit window shifted into place, two bits per register spread to the
     // two u16 halves.  An S of 0xffff elsewhere gives the same minimum.
     uint32_t second = 0xffffu;
-    if (VIEW == 0 && a.feat) {
+    if (VIEW == 0 && (stage.on ? stage.feat : a.feat != nullptr)) {
         const int e = db - d0;
         const uint32_t win = (e >= -1 && e <= K) ? ((0x7u << (e + 7)) >> 8) : 0u;
         uint32_t mn = 0xffffffffu;
@@ -422,7 +447,7 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
         if (stage.on) stage.d[0] = (int16_t)db;
         else a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
-            uint32_t A = 0, B = best >> 9, Cc = 0;   // S(d*) is the minimum itself
+            uint32_t A = 0, B = best >> 16, Cc = 0;  // S(d*) is the minimum itself
             if (simg) {
                 A = db > 0 ? simg[db - 1] : 0u;
                 Cc = db < D - 1 ? simg[db + 1] : 0u;
@@ -445,18 +470,16 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
                     }
                 }
             }
-            float v = (float)db;
+            const int num = (int)A - (int)Cc;
             const int den = (int)A - 2 * (int)B + (int)Cc;
-            if (a.subpixel && db > 0 && db < D - 1 && den > 0)
-                v = (float)db + __fdiv_rn((float)((int)A - (int)Cc), (float)(2 * den));
             const uint32_t f0 = B | (second << 16);
             const uint32_t f1 = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
             if (stage.on) {
-                stage.v[0] = v;
+                stage.num[0] = num;
                 stage.f[0] = f0;
                 stage.f[1] = f1;
             } else {
-                a.dsub[px] = v;
+                a.dsub[px] = subpixel_value(a.subpixel, db, num, (int)f1);
                 if (a.feat) {
                     a.feat[2 * px] = f0;
                     a.feat[2 * px + 1] = f1;
