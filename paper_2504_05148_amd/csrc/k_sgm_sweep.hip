@@ -41,6 +41,8 @@
 // from the left or the top stay zero there and each path starts with L = C
 // as Eq. 2 starts a path; dl states leaving past the right end are replaced
 // by zero (the dl path starts at the last pixel of the next row).
+#include <type_traits>
+
 #include "sgm_common.h"
 
 namespace sldf {
@@ -74,6 +76,12 @@ struct SweepLds {
     uint32_t xm[2][NX][ROWS + 1];
     uint32_t pat[pattern_words(G * 8)];
     int ticket;
+};
+
+// A step's loads in sweep A: the base pixel's code, the matching code that
+// enters the lane's run, the prior word
+struct SweepWinIn {
+    uint32_t cb, mnew, w;
 };
 
 // pass-coordinate position u of row j at step t
@@ -111,13 +119,13 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
     const uint32_t p1x2 = a.p1s * 0x10001u, p2x2 = a.p2s * 0x10001u;
     const bool gfirst = g == 0, glast = g == G - 1;
     const int W = a.W;
+    // the feature switch as a scalar (the compiler otherwise rebuilds it from
+    // a lane mask in every step)
+    const bool want_feat = __builtin_amdgcn_readfirstlane(a.feat != nullptr ? 1 : 0) != 0;
     // the wave's first and last rows: a step where all of them are before
     // their row (u < 0), past it by more than one pixel, or outside the band
     // / image is skipped as a whole (states stay zero before the row; the dl
     // output at u = W, the last one the row below reads, is still written)
-    // the feature switch as a scalar (the compiler otherwise rebuilds it from
-    // a lane mask in every step)
-    const bool want_feat = __builtin_amdgcn_readfirstlane(a.feat != nullptr ? 1 : 0) != 0;
     const int j0 = j - j % RPW;
     const bool wave_dead = j0 >= rpb || band * rpb + j0 >= a.H;
     Edge edge;
@@ -127,30 +135,83 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
     uint32_t drq1[NR] = {}, mdrq1 = 0;          // dr inputs of the next two steps
     uint32_t drq2[NR] = {}, mdrq2 = 0;
 
-    StepIn<NR> R[kRing];
+    // Sweep A: the lane's K matching codes move by one address per step (dx),
+    // so a step loads only the code that enters the run.  The codes live in a
+    // register window: at step t the code of ascending index e (the lane's
+    // first matching address + e) is in slot (e + (t - t0) dx) mod K, the
+    // entering code (e = K - 1 for dx = 1, e = 0 for dx = -1) takes the slot
+    // of the one that leaves, and with the step loop unrolled by K every slot
+    // index is a constant.  The entering codes are read unclamped from K
+    // positions before the row (the census rows' pads and guard rows hold
+    // them), so the window is exact from the row's first pixel on; positions
+    // before that cost 0 whatever their codes (guard weight 0).  Sweep B,
+    // short of registers and instruction-bound, loads the whole run per step.
+    constexpr bool kWin = PASS == 0;
+    constexpr int U = kWin ? K : kRing;         // steps per loop iteration
+    typename std::conditional<kWin, SweepWinIn, StepIn<NR>>::type R[kRing];
     vecT<NR> SA[kRing];
+    uint32_t win[K];
+    typedef __attribute__((address_space(1))) const uint32_t* gu32;
+    const uint32_t mnew_off = dx > 0 ? 4u * (K - 1) : 0u;
     auto load = [&](int i, int u) {
         const int uc = min(max(u, -1), W);
-        load_pixel<VIEW>(la, la.at(uc), R[i]);
+        if constexpr (kWin) {
+            // offsets summed in 32 bits before they meet the base (a step
+            // before the row start is a negative product that the sum wraps
+            // back into the row's pads)
+            const int um = min(max(u, -K), W);
+            const PixOff o = la.at(uc);
+            const uint32_t om = la.om0 + (uint32_t)__mul24(um, la.dc) + mnew_off;
+            R[i].cb = *reinterpret_cast<gu32>(la.cbase + o.oc);
+            R[i].mnew = *reinterpret_cast<gu32>(la.cmatch + om);
+            R[i].w = *reinterpret_cast<gu32>(la.prior + o.op);
+        } else {
+            load_pixel<VIEW>(la, la.at(uc), R[i]);
+        }
         if (kLast) SA[i] = load_s<NR>(la, la.at(min(max(u, 0), W - 1)));
     };
-    // joint cost of position u from ring slot i (0 at virtual positions:
-    // they read the guard position)
-    auto cost = [&](int i, int u, uint32_t C[NR]) {
+    // joint cost of position u from ring slot i, s = (t - t0) mod K of its
+    // step t (0 at virtual positions: they read the guard position)
+    auto cost_at = [&](int i, int s, int u, uint32_t C[NR]) {
         const int uc = min(max(u, -1), W);
-        cost_lane<D, VIEW, NR>(a, patl, R[i], x0 + uc * dx, d0, C);
+        if constexpr (kWin) {
+            uint32_t asc[K];
+#pragma unroll
+            for (int e = 0; e < K; ++e) asc[e] = win[(e + s * dx + 8 * K) % K];
+            cost_codes<D, VIEW, NR>(a, patl, R[i].cb, asc, R[i].w, x0 + uc * dx, d0, C);
+        } else {
+            cost_lane<D, VIEW, NR>(a, patl, R[i], x0 + uc * dx, d0, C);
+        }
+    };
+    // the entering code of the step with window index s, then its cost
+    auto cost = [&](int i, int s, int u, uint32_t C[NR]) {
+        if constexpr (kWin) win[((dx > 0 ? K - 1 : 0) + s * dx + 8 * K) % K] = R[i].mnew;
+        cost_at(i, s, u, C);
     };
     const int t0 = -2;
 #pragma unroll
     for (int i = 0; i < kRing; ++i) load(i, sw_pos(t0 + i, j));
+    if constexpr (kWin) {
+        // the whole run of the first step (window index 0: slot e = index e)
+        const int um = min(max(sw_pos(t0, j), -K), W);
+        typedef __attribute__((address_space(1))) const u32x4a4* gu32x4;
+        const gcptr pm = la.cmatch + (la.om0 + (uint32_t)__mul24(um, la.dc));
+        const u32x4a4 lo = *reinterpret_cast<gu32x4>(pm), hi = *reinterpret_cast<gu32x4>(pm + 16);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            win[e] = lo[e];
+            win[4 + e] = hi[e];
+        }
+    }
     // the cost of a step is computed at the end of the step before
     uint32_t C[NR];
-    cost(0, sw_pos(t0, j), C);
+    cost_at(0, 0, sw_pos(t0, j), C);
 
-    for (int tb = t0; tb < T; tb += kRing) {
+    for (int tb = t0; tb < T; tb += U) {
 #pragma unroll
-        for (int i = 0; i < kRing; ++i) {
-            const int t = tb + i;
+        for (int ii = 0; ii < U; ++ii) {
+            const int i = ii % kRing;
+            const int t = tb + ii;
             const int u = sw_pos(t, j);
             const int si = (t - 1) & 1, so = t & 1;
             const bool skip =
@@ -176,6 +237,7 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
             }
             const vecT<NR> sa = SA[i];
             const int inext = (i + 1) % kRing;
+            const int snext = (ii + 1) % K;           // window index of step t + 1
             // sweep A: ring slot i (this step's inputs, consumed at the end of
             // the step before) takes those of step t + kRing, issued before this
             // step's S store, so that waiting for them never waits for that store
@@ -214,7 +276,7 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                     }
                 }
                 // cost of the next step (its inputs were loaded a step ago)
-                cost(inext, u + 1, C);
+                cost(inext, snext, u + 1, C);
                 if (live && u >= 0 && u < W) {
                     const PixOff o = la.at(u);
                     if (!kLast) {
@@ -280,7 +342,7 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                 }
             } else if (!wave_dead) {
                 // the wave's rows have not started: the next step's cost
-                cost(inext, u + 1, C);
+                cost(inext, snext, u + 1, C);
             }
             // delay lines: dn of the row above for the next step, dr for the one after
 #pragma unroll

@@ -256,23 +256,19 @@ __device__ __forceinline__ void store_s(const LineAddr& la, const PixOff& o, con
 // guard ring the weight is 0 and the entry a zero run, so the virtual
 // positions before a line start cost 0: from a zero state L = 0, m = 0 such a
 // step leaves the state at zero, and the first real pixel then yields L = C
-// as Eq. 2 starts a path.
+// as Eq. 2 starts a path.  Inputs: the base pixel's code cb, the lane's K
+// matching codes in ascending address order (asc[e] is the code at the
+// lane's first matching address + e) and the pixel's prior word w.
 template <int D, int VIEW, int NR = 4>
-__device__ __forceinline__ void cost_lane(const SgmArgs& a, const char* patl,
-                                          const StepIn<NR>& in, int x, int d0, uint32_t C[NR])
+__device__ __forceinline__ void cost_codes(const SgmArgs& a, const char* patl, uint32_t cb,
+                                           const uint32_t asc[2 * NR], uint32_t w, int x, int d0,
+                                           uint32_t C[NR])
 {
     constexpr int K = 2 * NR;
-    // in.m holds the K matching codes in ascending address order: x - d
-    // descends with d for the left base, x + d ascends for the right base
-    uint32_t mc[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const int e = VIEW == 0 ? K - 1 - j : j;
-        mc[j] = in.m[e / 4][e % 4];
-    }
+    // x - d descends with d for the left base, x + d ascends for the right base
     uint32_t h[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) h[j] = __builtin_popcount(in.cb ^ mc[j]);
+    for (int j = 0; j < K; ++j) h[j] = __builtin_popcount(cb ^ asc[VIEW == 0 ? K - 1 - j : j]);
     if (VIEW == 0 ? x < d0 + K - 1 : x + d0 + K - 1 >= a.W) {
         // distance of the lane's first matching pixel from the image edge;
         // opaque, so that the compiler derives the K tests here instead of
@@ -283,9 +279,9 @@ __device__ __forceinline__ void cost_lane(const SgmArgs& a, const char* patl,
         for (int j = 0; j < K; ++j) h[j] = k < j ? (uint32_t)a.n : h[j];
     }
     // the weight (low half of the word) multiplies both halves
-    const u16x2 wt = __builtin_shufflevector(v2(in.w), v2(in.w), 0, 0);
+    const u16x2 wt = __builtin_shufflevector(v2(w), v2(w), 0, 0);
     if (VIEW == 0) {
-        const uint32_t* p = reinterpret_cast<const uint32_t*>(patl + (in.w >> 16));
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(patl + (w >> 16));
 #pragma unroll
         for (int i = 0; i < NR; ++i)
             C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt + v2(p[i]));
@@ -293,6 +289,18 @@ __device__ __forceinline__ void cost_lane(const SgmArgs& a, const char* patl,
 #pragma unroll
         for (int i = 0; i < NR; ++i) C[i] = u1(v2(h[2 * i] | (h[2 * i + 1] << 16)) * wt);
     }
+}
+
+// The same from one pixel's loads (load_pixel); in.m holds the K matching
+// codes in ascending address order.
+template <int D, int VIEW, int NR = 4>
+__device__ __forceinline__ void cost_lane(const SgmArgs& a, const char* patl,
+                                          const StepIn<NR>& in, int x, int d0, uint32_t C[NR])
+{
+    uint32_t asc[2 * NR];
+#pragma unroll
+    for (int e = 0; e < 2 * NR; ++e) asc[e] = in.m[e / 4][e % 4];
+    cost_codes<D, VIEW, NR>(a, patl, in.cb, asc, in.w, x, d0, C);
 }
 
 // Minimum of the lane's K cells, in both halves of the result.
