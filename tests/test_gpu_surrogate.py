@@ -365,3 +365,54 @@ def test_committed_weights_agree_with_plain_check_on_heldout_frames():
     agree = float((vl == vp).float().mean())
     print(f"held-out agreement {agree:.5f}", flush=True)
     assert agree >= 0.99
+
+
+def test_learned_bench_launch_configuration():
+    """The learned check in the benchmark's launch configuration at 1242 x 375,
+    D = 128: one 128-frame call, and two contexts of 64 frames on two streams
+    (twice), bit for bit equal; sampled frames equal single-frame learned
+    runs (the convolutions sum in a fixed order whatever their tiling)."""
+    from paper_2504_05148_amd.train_surrogate import load_weights
+    w, b, _ = load_weights()
+    base = [synth.kitti_frame(i) for i in range(16)]
+    # distinct frames of the same shape: each copy rolled by its own offset
+    frames = [dict(base[i % 16], **{c: np.roll(base[i % 16][c], 7 * (i // 16), axis=1)
+                                    for c in ("left", "right", "lidar")}) for i in range(128)]
+    B, D = len(frames), 128
+    left = sldf.device_images(np.stack([f["left"] for f in frames]))
+    right = sldf.device_images(np.stack([f["right"] for f in frames]))
+    lid = torch.stack([sldf.quantize_lidar(torch.from_numpy(f["lidar"]).cuda(), D)
+                       for f in frames])
+    print("case learned one 128-frame call", flush=True)
+    c = sldf.Context(sldf.default_params(batch=B, check_impl=1))
+    c.set_surrogate(w, b)
+    d_all, v_all = c.run_batch(left, right, lid)
+    torch.cuda.synchronize()
+    del c
+    print("case learned 2 streams x 64 frames", flush=True)
+    n = B // 2
+    streams = (torch.cuda.current_stream(), torch.cuda.Stream())
+    ctxs = []
+    for _ in range(2):
+        ci = sldf.Context(sldf.default_params(batch=n, check_impl=1))
+        ci.set_surrogate(w, b)
+        ctxs.append(ci)
+    outs = [ci.new_outputs(n) for ci in ctxs]
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for i, st in enumerate(streams):
+            sl = slice(i * n, (i + 1) * n)
+            ctxs[i].run_batch(left[sl], right[sl], lid[sl], outs[i][0], outs[i][1], stream=st)
+        torch.cuda.synchronize()
+        for i in range(2):
+            sl = slice(i * n, (i + 1) * n)
+            assert torch.equal(outs[i][1], v_all[sl]), (rep, i)
+            assert torch.equal(outs[i][0], d_all[sl]), (rep, i)
+    del ctxs, outs
+    print("case learned single frames", flush=True)
+    c1 = sldf.Context(sldf.default_params(batch=1, check_impl=1))
+    c1.set_surrogate(w, b)
+    for i in (0, 63, 64, B - 1):
+        d1, v1 = c1.run(left[i], right[i], lid[i])
+        torch.cuda.synchronize()
+        assert torch.equal(v1, v_all[i]) and torch.equal(d1, d_all[i]), i
