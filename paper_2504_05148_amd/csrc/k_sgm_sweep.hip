@@ -148,6 +148,9 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
     // short of registers and instruction-bound, loads the whole run per step.
     constexpr bool kWin = PASS == 0;
     constexpr int U = kWin ? K : kRing;         // steps per loop iteration
+    // T + 2 is a multiple of the loader's unroll: every wave runs the same
+    // number of steps, so of barriers
+    static_assert(kSwAhead % U == 0 && U % kRing == 0, "step unrolls must divide kSwAhead");
     typename std::conditional<kWin, SweepWinIn, StepIn<NR>>::type R[kRing];
     vecT<NR> SA[kRing];
     uint32_t win[K];
