@@ -95,8 +95,8 @@ __device__ __forceinline__ int sw_pos(int t, int j) { return t - 2 * j; }
 template <int G>
 struct SweepStage {
     int16_t d[2 * G];
-    int32_t num[2 * G];     // S(d*-1) - S(d*+1)
-    uint32_t f[4 * G];      // cost-feature words; f[2i + 1] is the parabola's denominator
+    uint32_t ac[2 * G];     // S(d*-1) | S(d*+1) << 16
+    uint32_t bs[2 * G];     // S(d*) | second minimum << 16 (the first cost-feature word)
 };
 
 template <int G, int PASS, int NP, int VIEW, int NW>
@@ -288,7 +288,8 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                         if (a.store_sum) store_s<NR>(la, o, St);
                         const int x = x0 + u * dx;
                         // the row's S(p, .) in LDS: the owner of d* reads its neighbours
-                        u32x4* srow = reinterpret_cast<u32x4*>(sbuf) + j * G;
+                        // (one u32x4 of padding before the first and after the last row)
+                        u32x4* srow = reinterpret_cast<u32x4*>(sbuf) + 1 + j * G;
                         srow[g] = pack_v<NR>(St);
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         // the pixel's outputs wait in the row's stage (slot x mod 2G)
@@ -296,12 +297,11 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                         SweepStage<G>& rs = ostage[j];
                         const int slot = (int)((uint32_t)x % (2u * G));   // x >= 0 here
                         typedef __attribute__((address_space(3))) int16_t li16;
-                        typedef __attribute__((address_space(3))) int32_t li32;
                         typedef __attribute__((address_space(3))) uint32_t lu32;
-                        const WtaStage ws{true, want_feat, (li16*)&rs.d[slot],
-                                          (li32*)&rs.num[slot], (lu32*)&rs.f[2 * slot]};
-                        wta_emit<G, VIEW, NR>(a, St, d0, 0, reinterpret_cast<const uint16_t*>(srow),
-                                              ws);
+                        const WtaStage ws{true, want_feat, (li16*)&rs.d[slot], (lu32*)&rs.ac[slot],
+                                          (lu32*)&rs.bs[slot]};
+                        wta_emit<G, VIEW, NR, true>(a, St, d0, 0,
+                                                    reinterpret_cast<const uint16_t*>(srow), ws);
                         if (slot == 0) {
                             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                             const size_t rowp = (size_t)frame * a.px_stride + (size_t)y * W;
@@ -310,13 +310,17 @@ __device__ __forceinline__ void sweep_compute(const SgmArgs& a, SweepLds<G, NP, 
                                 const int i = g + k * G;
                                 if (x + i < W) {
                                     const size_t p = rowp + x + i;
-                                    a.wta[VIEW][p] = rs.d[i];
+                                    const int db = rs.d[i];
+                                    a.wta[VIEW][p] = (int16_t)db;
                                     if (VIEW == 0) {
-                                        a.dsub[p] = subpixel_value(a.subpixel, rs.d[i], rs.num[i],
-                                                                   (int)rs.f[2 * i + 1]);
+                                        float v;
+                                        uint32_t f1;
+                                        parabola_outputs<D>(a.subpixel, db, rs.ac[i], rs.bs[i], v,
+                                                            f1);
+                                        a.dsub[p] = v;
                                         if (want_feat) {
-                                            a.feat[2 * p] = rs.f[2 * i];
-                                            a.feat[2 * p + 1] = rs.f[2 * i + 1];
+                                            a.feat[2 * p] = rs.bs[i];
+                                            a.feat[2 * p + 1] = f1;
                                         }
                                     }
                                 }
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(NW * 64, 4) void sgm_sweep_kernel(SgmArgs a)
     constexpr int ROWS = sweep_rows<G, NW>();
     constexpr int D = G * 8;
     __shared__ SweepLds<G, NP, NW> sm;
-    __shared__ u32x4 sbuf[PASS == 1 ? ROWS * G : 1];
+    __shared__ u32x4 sbuf[PASS == 1 ? ROWS * G + 2 : 1];
     __shared__ SweepStage<G> ostage[PASS == 1 ? ROWS : 1];
     const int tid = threadIdx.x;
     if (tid == 0)

@@ -380,16 +380,16 @@ __device__ __forceinline__ void rec_lane(uint32_t L[NR], uint32_t& m, const uint
 }
 
 // Where wta_emit puts the owner lane's outputs of a pixel: with on false, to
-// global memory at px; otherwise to these LDS slots (d*, the numerator of
-// the parabola offset and the two cost-feature words, the second of which
-// is its denominator), which the caller writes out later with other pixels
-// of the row in whole cache lines, taking the division there.
+// global memory at px; otherwise to these LDS slots, which the caller writes
+// out later with other pixels of the row in whole cache lines, taking the
+// parabola there: d*, S(d*-1) | S(d*+1) << 16 and S(d*) | second << 16 (the
+// first cost-feature word; left view only).
 struct WtaStage {
     bool on = false;
     bool feat = false;      // with on: the cost features are wanted (a.feat not null)
     __attribute__((address_space(3))) int16_t* d = nullptr;
-    __attribute__((address_space(3))) int32_t* num = nullptr;
-    __attribute__((address_space(3))) uint32_t* f = nullptr;
+    __attribute__((address_space(3))) uint32_t* ac = nullptr;
+    __attribute__((address_space(3))) uint32_t* bs = nullptr;
 };
 
 // Subpixel disparity of the parabola through S(d*-1), S(d*), S(d*+1):
@@ -404,13 +404,30 @@ __device__ __forceinline__ float subpixel_value(int subpixel, int db, int num, i
     return v;
 }
 
+// The left view's outputs of a pixel from d* = db and its staged words ac =
+// S(d*-1) | S(d*+1) << 16 (either half arbitrary at its end of the range) and
+// bs = S(d*) | second << 16: the subpixel disparity and the two cost-feature
+// words (bs itself and the parabola's denominator, 0 at the range ends).
+template <int D>
+__device__ __forceinline__ void parabola_outputs(int subpixel, int db, uint32_t ac, uint32_t bs,
+                                                 float& v, uint32_t& f1)
+{
+    const int A = (int)(ac & 0xffffu), Cc = (int)(ac >> 16), B = (int)(bs & 0xffffu);
+    const int den = A - 2 * B + Cc;
+    f1 = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+    v = subpixel_value(subpixel, db, A - Cc, (int)f1);
+}
+
 // Winner-takes-all on the aggregated cost St (Eq. 3; lexicographic minimum
 // of (S, d), ties -> smallest d) and the parabola fit through S(d*-1),
 // S(d*), S(d*+1); the owning lane writes d* (and for the left view the
 // subpixel disparity and the learned-check cost features).  simg, when not
 // null, is the line's S(p, .) as D u16 in LDS (written by the group before
-// the call), from which the owner reads the two neighbours of d*.
-template <int G, int VIEW, int NR = 4>
+// the call), from which the owner reads the two neighbours of d*.  With
+// kPadded, simg is never null and one u16 before and after the line is
+// readable, so the owner reads both neighbours without range tests (what
+// they hold at the range ends is not used).
+template <int G, int VIEW, int NR = 4, bool kPadded = false>
 __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR], int d0,
                                          size_t px, const uint16_t* simg = nullptr,
                                          const WtaStage& stage = WtaStage{})
@@ -428,8 +445,9 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
     }
     best = group_min<G>(best + (uint32_t)d0);
     const int db = (int)(best & 0xffffu);
-    const uint32_t spv = simg ? 0u : dpp<kWaveShr1>(St[NR - 1]);
-    const uint32_t snx = simg ? 0u : dpp<kWaveShl1>(St[0]);
+    const bool lds_row = kPadded || simg != nullptr;
+    const uint32_t spv = lds_row ? 0u : dpp<kWaveShr1>(St[NR - 1]);
+    const uint32_t snx = lds_row ? 0u : dpp<kWaveShl1>(St[0]);
     // learned-check cost feature: second minimum of S over |d - d*| >= 2.  The
     // lane's cells d* - 1 .. d* + 1 (local indices e - 1 .. e + 1, e = d* - d0)
     // are set to 0xffff in packed form before a packed minimum: bits of the
@@ -456,7 +474,10 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
         else a.wta[VIEW][px] = (int16_t)db;
         if (VIEW == 0) {
             uint32_t A = 0, B = best >> 16, Cc = 0;  // S(d*) is the minimum itself
-            if (simg) {
+            if (kPadded) {
+                A = simg[db - 1];
+                Cc = simg[db + 1];
+            } else if (simg) {
                 A = db > 0 ? simg[db - 1] : 0u;
                 Cc = db < D - 1 ? simg[db + 1] : 0u;
             } else {
@@ -478,16 +499,15 @@ __device__ __forceinline__ void wta_emit(const SgmArgs& a, const uint32_t St[NR]
                     }
                 }
             }
-            const int num = (int)A - (int)Cc;
-            const int den = (int)A - 2 * (int)B + (int)Cc;
-            const uint32_t f0 = B | (second << 16);
-            const uint32_t f1 = (db > 0 && db < D - 1) ? (uint32_t)den : 0u;
+            const uint32_t ac = A | (Cc << 16), f0 = B | (second << 16);
             if (stage.on) {
-                stage.num[0] = num;
-                stage.f[0] = f0;
-                stage.f[1] = f1;
+                stage.ac[0] = ac;
+                stage.bs[0] = f0;
             } else {
-                a.dsub[px] = subpixel_value(a.subpixel, db, num, (int)f1);
+                float v;
+                uint32_t f1;
+                parabola_outputs<D>(a.subpixel, db, ac, f0, v, f1);
+                a.dsub[px] = v;
                 if (a.feat) {
                     a.feat[2 * px] = f0;
                     a.feat[2 * px + 1] = f1;
