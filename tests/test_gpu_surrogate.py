@@ -367,17 +367,14 @@ def test_committed_weights_agree_with_plain_check_on_heldout_frames():
     assert agree >= 0.99
 
 
-def test_learned_bench_launch_configuration():
+def test_learned_bench_launch_configuration(bench_frames):
     """The learned check in the benchmark's launch configuration at 1242 x 375,
     D = 128: one 128-frame call, and two contexts of 64 frames on two streams
     (twice), bit for bit equal; sampled frames equal single-frame learned
     runs (the convolutions sum in a fixed order whatever their tiling)."""
     from paper_2504_05148_amd.train_surrogate import load_weights
     w, b, _ = load_weights()
-    base = [synth.kitti_frame(i) for i in range(16)]
-    # distinct frames of the same shape: each copy rolled by its own offset
-    frames = [dict(base[i % 16], **{c: np.roll(base[i % 16][c], 7 * (i // 16), axis=1)
-                                    for c in ("left", "right", "lidar")}) for i in range(128)]
+    frames = bench_frames
     B, D = len(frames), 128
     left = sldf.device_images(np.stack([f["left"] for f in frames]))
     right = sldf.device_images(np.stack([f["right"] for f in frames]))
